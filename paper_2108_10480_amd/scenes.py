@@ -1,0 +1,209 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module only builds geometry and query sets: vertices, primitive index
+tuples, query points.  It holds none of the smooth-distance arithmetic (no
+distances, weights, log-sum-exp or hierarchy), so both the HIP path and the
+FP64 reference read identical FP32 arrays produced here.
+
+The paper's own data (Thingi10K meshes, the Stanford bunny, Toronto-3D street
+lidar, OpenTopography terrain) is not available, so every scene below is a
+synthetic stand-in with the shapes and sizes of the paper's workloads
+(Sec. 4.4 benchmark, Table 1 lidar scenes).
+
+All arrays are numpy: vertices ``V`` float32 (n, 3); point ids ``P`` int32
+(n,), edges ``E`` int32 (n, 2), triangles ``T`` int32 (n, 3); queries ``Q``
+float32 (n, 3).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Scene:
+    V: np.ndarray                      # (nV, 3) float32
+    P: np.ndarray | None = None        # (nP,) int32 vertex ids used as points
+    E: np.ndarray | None = None        # (nE, 2) int32
+    T: np.ndarray | None = None        # (nT, 3) int32
+    name: str = ""
+
+    def counts(self):
+        return (0 if self.P is None else len(self.P),
+                0 if self.E is None else len(self.E),
+                0 if self.T is None else len(self.T))
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+# --------------------------------------------------------------------------
+# basic shapes
+# --------------------------------------------------------------------------
+_PHI = (1.0 + 5.0 ** 0.5) / 2.0
+_ICO_V = np.array([
+    [-1, _PHI, 0], [1, _PHI, 0], [-1, -_PHI, 0], [1, -_PHI, 0],
+    [0, -1, _PHI], [0, 1, _PHI], [0, -1, -_PHI], [0, 1, -_PHI],
+    [_PHI, 0, -1], [_PHI, 0, 1], [-_PHI, 0, -1], [-_PHI, 0, 1]], dtype=np.float64)
+_ICO_F = np.array([
+    [0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+    [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+    [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+    [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
+
+
+def icosphere(level: int):
+    """Unit icosphere after ``level`` midpoint subdivisions (float64 V, int64 F).
+
+    V = 10*4^level + 2, F = 20*4^level, E = 30*4^level.
+    """
+    V = _ICO_V / np.linalg.norm(_ICO_V, axis=1, keepdims=True)
+    F = _ICO_F.copy()
+    for _ in range(level):
+        nV, nF = len(V), len(F)
+        e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
+        es = np.sort(e, axis=1)
+        uniq, inv = np.unique(es, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        mid = 0.5 * (V[uniq[:, 0]] + V[uniq[:, 1]])
+        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
+        m = inv.reshape(3, nF).T + nV          # midpoints of (01, 12, 20)
+        a, b, c = F[:, 0], F[:, 1], F[:, 2]
+        m01, m12, m20 = m[:, 0], m[:, 1], m[:, 2]
+        F = np.concatenate([
+            np.stack([a, m01, m20], 1), np.stack([m01, b, m12], 1),
+            np.stack([m20, m12, c], 1), np.stack([m01, m12, m20], 1)])
+        V = np.concatenate([V, mid])
+    return V, F
+
+
+def torus_grid(nu: int, nv: int, R: float, r: float):
+    """Closed torus triangulated on an nu x nv grid (every vertex has valence 6)."""
+    u = 2 * np.pi * np.arange(nu) / nu
+    v = 2 * np.pi * np.arange(nv) / nv
+    uu, vv = np.meshgrid(u, v, indexing="ij")
+    X = np.stack([(R + r * np.cos(vv)) * np.cos(uu),
+                  (R + r * np.cos(vv)) * np.sin(uu),
+                  r * np.sin(vv)], -1).reshape(-1, 3)
+    i, j = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    i, j = i.reshape(-1), j.reshape(-1)
+    a = i * nv + j
+    b = ((i + 1) % nu) * nv + j
+    c = ((i + 1) % nu) * nv + (j + 1) % nv
+    d = i * nv + (j + 1) % nv
+    F = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)])
+    return X, F
+
+
+def grid_edges_of(F):
+    """Unique undirected edges of a triangle list, sorted (helper for edge scenes)."""
+    e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
+    return np.unique(np.sort(e, axis=1), axis=0)
+
+
+# --------------------------------------------------------------------------
+# point sphere (point-cloud workload, 2,000 points)
+# --------------------------------------------------------------------------
+def point_sphere(n_points=2000, n_queries=10000, seed_data=0, seed_query=1):
+    rng = np.random.default_rng(seed_data)
+    d = rng.standard_normal((n_points, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rad = 1.0 + rng.normal(0.0, 0.005, n_points)
+    V = _f32(d * rad[:, None])
+    Q = _f32(np.random.default_rng(seed_query).uniform(-1.5, 1.5, (n_queries, 3)))
+    return Scene(V=V, P=_i32(np.arange(n_points)), name="point_sphere"), Q
+
+
+# --------------------------------------------------------------------------
+# bumpy icosphere (triangle-mesh workload: level 7 = 327,680 triangles)
+# --------------------------------------------------------------------------
+def bumpy_icosphere(level=7, seed=2):
+    V, F = icosphere(level)
+    rng = np.random.default_rng(seed)
+    dirs = rng.standard_normal((8, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    k = rng.uniform(1.0, 6.0, 8)
+    ph = rng.uniform(0.0, 2 * np.pi, 8)
+    r = 1.0 + 0.05 * np.sin(V @ dirs.T * k + ph).sum(1)
+    V = V * r[:, None]
+    return Scene(V=_f32(V), T=_i32(F), name=f"bumpy_icosphere_l{level}")
+
+
+def triangle_areas_normals(V, T):
+    """Float64 areas and unit normals of the triangles (sampling helper)."""
+    V = V.astype(np.float64)
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    n = np.cross(b - a, c - a)
+    ln = np.linalg.norm(n, axis=1)
+    return 0.5 * ln, n / np.maximum(ln, 1e-300)[:, None]
+
+
+def surface_samples(V, T, n, rng, offset_lo, offset_hi):
+    """Area-weighted uniform points on the triangles, moved along the face
+    normal by U[offset_lo, offset_hi]."""
+    area, nrm = triangle_areas_normals(V, T)
+    cdf = np.cumsum(area)
+    cdf /= cdf[-1]
+    tri = np.minimum(np.searchsorted(cdf, rng.random(n)), len(T) - 1)
+    r1, r2 = rng.random(n), rng.random(n)
+    flip = r1 + r2 > 1.0
+    r1[flip], r2[flip] = 1.0 - r1[flip], 1.0 - r2[flip]
+    Vd = V.astype(np.float64)
+    a, b, c = Vd[T[tri, 0]], Vd[T[tri, 1]], Vd[T[tri, 2]]
+    p = a + r1[:, None] * (b - a) + r2[:, None] * (c - a)
+    off = rng.uniform(offset_lo, offset_hi, n)
+    return p + off[:, None] * nrm[tri]
+
+
+def icosphere_queries(scene, n_queries=1_000_000, seed_box=3, seed_surf=4, box=1.5,
+                      band=0.02):
+    """Half uniform in [-box, box]^3, half within +-band of the surface."""
+    n_box = n_queries // 2
+    n_surf = n_queries - n_box
+    qb = np.random.default_rng(seed_box).uniform(-box, box, (n_box, 3))
+    qs = surface_samples(scene.V, scene.T, n_surf, np.random.default_rng(seed_surf),
+                         -band, band)
+    return _f32(np.concatenate([qb, qs]))
+
+
+# --------------------------------------------------------------------------
+# small random scenes for unit tests
+# --------------------------------------------------------------------------
+def random_points(n, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    V = _f32(rng.uniform(-scale, scale, (n, 3)))
+    return Scene(V=V, P=_i32(np.arange(n)), name=f"rand_points_{n}")
+
+
+def random_polyline(n_seg, seed, closed=False):
+    """A random-walk polyline (interior vertices have edge valence 2)."""
+    rng = np.random.default_rng(seed)
+    steps = rng.normal(0.0, 0.3, (n_seg + 1, 3))
+    V = np.cumsum(steps, axis=0)
+    nv = n_seg if closed else n_seg + 1
+    V = V[:nv]
+    E = np.stack([np.arange(n_seg), (np.arange(n_seg) + 1) % nv], 1)
+    return Scene(V=_f32(V), E=_i32(E), name=f"polyline_{n_seg}")
+
+
+def uniform_queries(n, seed, lo, hi):
+    return _f32(np.random.default_rng(seed).uniform(lo, hi, (n, 3)))
+
+
+def scene_aabb(scene):
+    V = scene.V
+    used = []
+    if scene.P is not None:
+        used.append(V[scene.P])
+    if scene.E is not None:
+        used.append(V[scene.E.reshape(-1)])
+    if scene.T is not None:
+        used.append(V[scene.T.reshape(-1)])
+    X = np.concatenate(used) if used else np.zeros((1, 3), np.float32)
+    return X.min(0).astype(np.float64), X.max(0).astype(np.float64)
