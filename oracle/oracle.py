@@ -424,9 +424,18 @@ def rigid_adjoint(X, R, gbar, grad):
 # --------------------------------------------------------------------------
 # Error measures used by the parity tests
 # --------------------------------------------------------------------------
-def value_error(d, d_ref, floor):
-    """|d - d_ref| / max(|d_ref|, floor)."""
-    return np.abs(np.asarray(d, np.float64) - d_ref) / np.maximum(np.abs(d_ref), floor)
+def value_error(d, d_ref, floor, dmin=None):
+    """|d - d_ref| / max(|d_ref|, d_min, floor).
+
+    Relative error measured against the magnitudes the log-sum-exp combines:
+    the result d = d* - log(sum)/alpha cancels two terms of size up to the
+    nearest distance d_min where it crosses zero, so d_min (when given) joins
+    |d_ref| in the denominator; ``floor`` (1e-3 of the scene diagonal in the
+    tests) covers queries on the data itself."""
+    den = np.maximum(np.abs(d_ref), floor)
+    if dmin is not None:
+        den = np.maximum(den, np.asarray(dmin, np.float64))
+    return np.abs(np.asarray(d, np.float64) - d_ref) / den
 
 
 def grad_error(g, g_ref, floor=1e-2):

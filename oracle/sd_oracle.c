@@ -140,7 +140,20 @@ static void triangle_closest(v3 q, v3 v0, v3 v1, v3 v2, closest *o) {
     /* boundary: edges (v0,v1) -> phi=(t,0); (v1,v2) -> phi=(1-t,t); (v2,v0) -> phi=(0,1-t) */
     v3 A[3] = {v0, v1, v2}, B[3] = {v1, v2, v0};
     double best = INFINITY; int bi = 0; double bt = 0; int bint = 0;
-    for (int k = 0; k < 3; ++k) {
+    int degenerate = !(dot(n, n) > 0.0 && det > 0.0);
+    if (degenerate) {
+        /* zero area (the paper is silent): the triangle is its longest edge,
+         * which covers the other two, so the closest point and barycentrics
+         * do not depend on how ties between the three edges are broken */
+        double lmax = -1.0;
+        for (int k = 0; k < 3; ++k) {
+            double l = dot(sub(B[k], A[k]), sub(B[k], A[k]));
+            if (l > lmax) { lmax = l; bi = k; }
+        }
+        bt = seg_t(q, A[bi], B[bi], &bint);
+        best = norm(sub(q, add(A[bi], scl(sub(B[bi], A[bi]), bt))));
+    }
+    for (int k = 0; k < 3 && !degenerate; ++k) {
         int interior;
         double t = seg_t(q, A[k], B[k], &interior);
         double d = norm(sub(q, add(A[k], scl(sub(B[k], A[k]), t))));

@@ -1,0 +1,56 @@
+"""Compile libsd.so (all HIP sources, gfx950) into the package directory.
+
+Usage: python -m paper_2108_10480_amd.csrc.build   (or build() from Python).
+Objects go to csrc/_build/; the shared library to paper_2108_10480_amd/libsd.so.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PKG = os.path.dirname(HERE)
+OUT = os.path.join(PKG, "libsd.so")
+OBJ = os.path.join(HERE, "_build")
+SOURCES = ["api.hip", "build.hip", "eval.hip", "sort.hip", "rigid.hip", "weights.cpp", "mlp.hip"]
+ARCH = os.environ.get("SD_OFFLOAD_ARCH", "gfx950")
+FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
+         # packed FP32 instructions are kept out of the device code
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-result"]
+
+
+def _compile(src):
+    path = os.path.join(HERE, src)
+    obj = os.path.join(OBJ, src + ".o")
+    cmd = ["hipcc", *FLAGS]
+    if src.endswith(".cpp"):
+        cmd += ["-x", "hip"]
+    cmd += ["-c", path, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    return obj
+
+
+def build(verbose=False):
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(_compile, srcs))
+    tmp = OUT + ".tmp"
+    cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, OUT)
+    if verbose:
+        print("built", OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

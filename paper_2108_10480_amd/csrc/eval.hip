@@ -1,0 +1,623 @@
+// Smooth-distance evaluation kernels.
+//
+//   k_eval     one lane per query: stackless depth-first traversal of each class
+//              hierarchy (Alg. 1), conservative far field (Sec. 3.5, App. D),
+//              exact leaf terms (App. B distances, App. C weights, Eq. 5
+//              weight gradients), online log-sum-exp (Eq. 3, Eq. 4), Alg. 2
+//              finalisation.
+//   k_brute    the same leaf terms over every primitive, primitives staged
+//              through LDS in tiles (beta = 0 semantics).
+//
+// Online log-sum-exp state per lane: the distance d* and log-weight l* of the
+// largest term so far, the sum s of exp(L_i - L*) and the gradient numerator
+// G, both with Neumaier compensation.  Exponents are formed as
+// alpha (d* - d_i) + (l_i - l*), so large alpha d never overflows and no
+// precision is lost to the magnitude of alpha d.  d = d* - (l* + log s)/alpha.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "sd_internal.h"
+
+namespace sd {
+namespace {
+
+constexpr int kB = 256;
+
+// Kahan's difference of products a*b - c*d with one FMA correction.
+__device__ __forceinline__ float dop(float a, float b, float c, float d) {
+    float w = c * d;
+    float e = fmaf(-c, d, w);
+    float f = fmaf(a, b, -w);
+    return f + e;
+}
+
+__device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+    return fmaf(ax, bx, fmaf(ay, by, az * bz));
+}
+
+struct LSE {
+    float dref, lref, s, sc;
+    float gx, gy, gz, cx, cy, cz;
+};
+
+__device__ __forceinline__ void neumaier(float &s, float &c, float x) {
+    float t = s + x;
+    bool big = fabsf(s) >= fabsf(x);
+    float a = big ? s : x, b = big ? x : s;
+    c += (a - t) + b;
+    s = t;
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void lse_add(LSE &st, float d, float lw, float gx, float gy, float gz,
+                                        float alpha) {
+    float t = fmaf(alpha, st.dref - d, lw - st.lref);   // L_i - L*
+    if (t <= 0.f) {
+        float e = __expf(t);
+        neumaier(st.s, st.sc, e);
+        if (GRAD) {
+            neumaier(st.gx, st.cx, e * gx);
+            neumaier(st.gy, st.cy, e * gy);
+            neumaier(st.gz, st.cz, e * gz);
+        }
+    } else {
+        float e = __expf(-t);
+        st.s *= e;
+        st.sc *= e;
+        neumaier(st.s, st.sc, 1.f);
+        if (GRAD) {
+            st.gx *= e; st.gy *= e; st.gz *= e;
+            st.cx *= e; st.cy *= e; st.cz *= e;
+            neumaier(st.gx, st.cx, gx);
+            neumaier(st.gy, st.cy, gy);
+            neumaier(st.gz, st.cz, gz);
+        }
+        st.dref = d;
+        st.lref = lw;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Triangle weight polynomial (App. C.3) in degree-7 Bernstein-Bezier form on
+// the barycentric triangle: w~ = sum_{i+j+k=7} b_ijk 7!/(i!j!k!) l0^i l1^j l2^k
+// with l1 = phi1, l2 = phi2, l0 = 1 - phi1 - phi2.  The basis is non-negative
+// and sums to one there, so FP32 evaluation stays within a few ulps.
+// Derivatives: d/dphi1 = 7 sum_{|m|=6} (b_{m+e1} - b_{m+e0}) B^6_m, likewise phi2.
+// ---------------------------------------------------------------------------
+struct Poly2 {
+    float w, wx, wy;
+};
+
+__host__ __device__ constexpr int bidx(int j, int k) { return j * 8 - (j * (j - 1)) / 2 + k; }
+
+// de Casteljau on the barycentric triangle: each level replaces the points of
+// degree n by convex combinations l0 c(i+1,j,k) + l1 c(i,j+1,k) + l2 c(i,j,k+1)
+// in place (slot (j, k), i implied).  The three degree-1 points give the value
+// and both partial derivatives: w_phi1 = 7 (c1 - c0), w_phi2 = 7 (c2 - c0).
+template <class Coef>
+__device__ __forceinline__ Poly2 tri_weight(const Coef &coef, float x, float y) {
+    float c[36];
+    coef.load(c);
+    const float l0 = 1.f - x - y;
+#pragma unroll
+    for (int n = 7; n >= 2; --n) {
+#pragma unroll
+        for (int j = 0; j <= n - 1; ++j) {
+#pragma unroll
+            for (int k = 0; j + k <= n - 1; ++k) {
+                c[bidx(j, k)] = fmaf(l0, c[bidx(j, k)], fmaf(x, c[bidx(j + 1, k)], y * c[bidx(j, k + 1)]));
+            }
+        }
+    }
+    Poly2 r;
+    const float c0 = c[bidx(0, 0)], c1 = c[bidx(1, 0)], c2 = c[bidx(0, 1)];
+    r.w = fmaf(l0, c0, fmaf(x, c1, y * c2));
+    r.wx = 7.f * (c1 - c0);
+    r.wy = 7.f * (c2 - c0);
+    return r;
+}
+
+struct CoefUniform {   // single valence class: coefficients in the kernel arguments
+    const EvalArgs &A;
+    __device__ __forceinline__ void load(float c[36]) const {
+#pragma unroll
+        for (int t = 0; t < 36; ++t) c[t] = A.tri_coef[t];
+    }
+};
+struct CoefTable {     // several classes: per-class rows of a device table (16-B aligned)
+    const float *row;
+    __device__ __forceinline__ void load(float c[36]) const {
+        const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            float4 v = r4[t];
+            c[4 * t] = v.x; c[4 * t + 1] = v.y; c[4 * t + 2] = v.z; c[4 * t + 3] = v.w;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Exact leaf terms.  Each returns the distance d, log-weight lw and, when
+// GRAD, g = grad d - grad(log w)/alpha (the Eq. 4 numerator direction).
+// ---------------------------------------------------------------------------
+// err bounds the FP32 rounding of d: the computed difference vectors are
+// exact up to a few ulps of the offset o from the vertex they are formed
+// against, so |d_fp32 - d| <= 2^-20 (d + |o|_1).  With conservative rounding
+// on (the default) each term enters the sum at d - err, so every term, and
+// hence the log-sum-exp, stays an underestimate (App. A) in FP32 too.
+struct Term {
+    float d, lw, gx, gy, gz, err;
+};
+
+template <bool GRAD>
+__device__ __forceinline__ Term point_term(float4 p, float qx, float qy, float qz) {
+    float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+    float d = sqrtf(dot3(dx, dy, dz, dx, dy, dz));
+    Term t{d, 0.f, 0.f, 0.f, 0.f, d * 0x1p-22f};
+    if (GRAD && d > 0.f) {
+        float inv = 1.f / d;
+        t.gx = dx * inv; t.gy = dy * inv; t.gz = dz * inv;
+    }
+    return t;
+}
+
+// segment v0 -> v1 with end weights a = 1/|N_0|, b = 1/|N_1| (App. C.2 quartic)
+template <bool GRAD>
+__device__ __forceinline__ Term edge_term(float4 r0, float4 r1, float qx, float qy, float qz,
+                                          float S, float slogA, float inv_alpha, bool metric) {
+    float ex = r1.x - r0.x, ey = r1.y - r0.y, ez = r1.z - r0.z;
+    float px = qx - r0.x, py = qy - r0.y, pz = qz - r0.z;
+    float ee = dot3(ex, ey, ez, ex, ey, ez);
+    float t = ee > 0.f ? dot3(px, py, pz, ex, ey, ez) / ee : 0.f;
+    bool interior = t > 0.f && t < 1.f;
+    t = fminf(fmaxf(t, 0.f), 1.f);
+    float cx = fmaf(-t, ex, px), cy = fmaf(-t, ey, py), cz = fmaf(-t, ez, pz);
+    float d = sqrtf(dot3(cx, cy, cz, cx, cy, cz));
+    float a = r0.w, b = r1.w;
+    float u = t * (1.f - t);
+    float bump = 16.f * (1.f - 0.5f * (a + b));
+    // w~ = a + (b - a)(3t^2 - 2t^3) + 16 (1 - (a+b)/2) t^2 (1-t)^2
+    float w = fmaf(b - a, t * t * (3.f - 2.f * t), fmaf(bump, u * u, a));
+    Term r{d, fmaf(S, __logf(w), slogA), 0.f, 0.f, 0.f,
+           (d + fabsf(px) + fabsf(py) + fabsf(pz)) * 0x1p-22f};
+    if (GRAD) {
+        float inv = d > 0.f ? 1.f / d : 0.f;
+        float gx = cx * inv, gy = cy * inv, gz = cz * inv;
+        if (interior) {
+            // dw~/dt = 6 (b - a) t (1 - t) + 2 bump t (1 - t)(1 - 2t)
+            float dw = u * fmaf(6.f, b - a, 2.f * bump * (1.f - 2.f * t));
+            float k = S * dw / (w * ee) * inv_alpha;
+            if (metric) k *= inv_alpha;
+            gx = fmaf(-k, ex, gx); gy = fmaf(-k, ey, gy); gz = fmaf(-k, ez, gz);
+        }
+        r.gx = gx; r.gy = gy; r.gz = gz;
+    }
+    return r;
+}
+
+// closest point of segment a + t e to p (for the degenerate-triangle fallback)
+__device__ __forceinline__ float seg_param(float px, float py, float pz, float ex, float ey, float ez) {
+    float ee = dot3(ex, ey, ez, ex, ey, ez);
+    float t = ee > 0.f ? dot3(px, py, pz, ex, ey, ez) / ee : 0.f;
+    return fminf(fmaxf(t, 0.f), 1.f);
+}
+
+// triangle (v0, v1, v2), barycentric phi1 <-> v1, phi2 <-> v2 (App. B).
+// Region classification after Ericson (Real-Time Collision Detection, 5.1.5)
+// with Kahan's FMA difference of products for the region determinants.
+template <bool GRAD>
+__device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float qx, float qy,
+                                         float qz, const EvalArgs &A, float slogA, bool metric) {
+    const float S = A.S, inv_alpha = A.inv_alpha;
+    float abx = r1.x - r0.x, aby = r1.y - r0.y, abz = r1.z - r0.z;
+    float acx = r2.x - r0.x, acy = r2.y - r0.y, acz = r2.z - r0.z;
+    float apx = qx - r0.x, apy = qy - r0.y, apz = qz - r0.z;
+    float d1 = dot3(abx, aby, abz, apx, apy, apz);
+    float d2 = dot3(acx, acy, acz, apx, apy, apz);
+    float bpx = qx - r1.x, bpy = qy - r1.y, bpz = qz - r1.z;
+    float d3 = dot3(abx, aby, abz, bpx, bpy, bpz);
+    float d4 = dot3(acx, acy, acz, bpx, bpy, bpz);
+    float cpx = qx - r2.x, cpy = qy - r2.y, cpz = qz - r2.z;
+    float d5 = dot3(abx, aby, abz, cpx, cpy, cpz);
+    float d6 = dot3(acx, acy, acz, cpx, cpy, cpz);
+    float vc = dop(d1, d4, d3, d2);
+    float vb = dop(d5, d2, d1, d6);
+    float va = dop(d3, d6, d5, d4);
+
+    // region: 0 face, 1 edge ab, 2 edge ac, 3 edge bc, 4 vertex
+    int region;
+    float p1, p2, t = 0.f;
+    float dx, dy, dz;      // q - closest point
+    float ex = 0.f, ey = 0.f, ez = 0.f;   // edge direction for the t gradient
+    float nx = dop(aby, acz, abz, acy), ny = dop(abz, acx, abx, acz), nz = dop(abx, acy, aby, acx);
+    float nn = dot3(nx, ny, nz, nx, ny, nz);
+    bool degenerate = !(nn > 0.f);
+    if (degenerate) {
+        // zero-area triangle: it is its longest edge (which covers the other
+        // two), first of ab, bc, ca on ties, so the barycentrics are unique
+        float bcx = r2.x - r1.x, bcy = r2.y - r1.y, bcz = r2.z - r1.z;
+        float lab = dot3(abx, aby, abz, abx, aby, abz), lbc = dot3(bcx, bcy, bcz, bcx, bcy, bcz);
+        float lac = dot3(acx, acy, acz, acx, acy, acz);
+        if (lab >= lbc && lab >= lac) {
+            t = seg_param(apx, apy, apz, abx, aby, abz);
+            p1 = t; p2 = 0.f; ex = abx; ey = aby; ez = abz;
+            dx = fmaf(-t, abx, apx); dy = fmaf(-t, aby, apy); dz = fmaf(-t, abz, apz);
+            region = (t > 0.f && t < 1.f) ? 1 : 4;
+        } else if (lbc >= lac) {
+            t = seg_param(bpx, bpy, bpz, bcx, bcy, bcz);
+            p1 = 1.f - t; p2 = t; ex = bcx; ey = bcy; ez = bcz;
+            dx = fmaf(-t, bcx, bpx); dy = fmaf(-t, bcy, bpy); dz = fmaf(-t, bcz, bpz);
+            region = (t > 0.f && t < 1.f) ? 3 : 4;
+        } else {
+            t = seg_param(apx, apy, apz, acx, acy, acz);
+            p1 = 0.f; p2 = t; ex = acx; ey = acy; ez = acz;
+            dx = fmaf(-t, acx, apx); dy = fmaf(-t, acy, apy); dz = fmaf(-t, acz, apz);
+            region = (t > 0.f && t < 1.f) ? 2 : 4;
+        }
+    } else if (d1 <= 0.f && d2 <= 0.f) {
+        region = 4; p1 = 0.f; p2 = 0.f; dx = apx; dy = apy; dz = apz;
+    } else if (d3 >= 0.f && d4 <= d3) {
+        region = 4; p1 = 1.f; p2 = 0.f; dx = bpx; dy = bpy; dz = bpz;
+    } else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
+        region = 1; t = d1 / (d1 - d3); p1 = t; p2 = 0.f;
+        ex = abx; ey = aby; ez = abz;
+        dx = fmaf(-t, abx, apx); dy = fmaf(-t, aby, apy); dz = fmaf(-t, abz, apz);
+    } else if (d6 >= 0.f && d5 <= d6) {
+        region = 4; p1 = 0.f; p2 = 1.f; dx = cpx; dy = cpy; dz = cpz;
+    } else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
+        region = 2; t = d2 / (d2 - d6); p1 = 0.f; p2 = t;
+        ex = acx; ey = acy; ez = acz;
+        dx = fmaf(-t, acx, apx); dy = fmaf(-t, acy, apy); dz = fmaf(-t, acz, apz);
+    } else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
+        region = 3; t = (d4 - d3) / ((d4 - d3) + (d5 - d6)); p1 = 1.f - t; p2 = t;
+        ex = r2.x - r1.x; ey = r2.y - r1.y; ez = r2.z - r1.z;
+        dx = fmaf(-t, ex, bpx); dy = fmaf(-t, ey, bpy); dz = fmaf(-t, ez, bpz);
+    } else {
+        region = 0;
+        float den = 1.f / (va + vb + vc);
+        p1 = vb * den; p2 = vc * den;
+        // distance to the plane through v0: |(q - v0) . n| / |n|, direction +-n
+        float inv_n = rsqrtf(nn);
+        float h = dot3(apx, apy, apz, nx, ny, nz) * inv_n;
+        dx = h * nx * inv_n; dy = h * ny * inv_n; dz = h * nz * inv_n;
+    }
+    float d = sqrtf(dot3(dx, dy, dz, dx, dy, dz));
+    Poly2 w = A.tri_uniform ? tri_weight(CoefUniform{A}, p1, p2)
+                            : tri_weight(CoefTable{A.tri_table + 36 * __float_as_int(r0.w)}, p1, p2);
+    float o = region <= 2 ? fabsf(apx) + fabsf(apy) + fabsf(apz)
+                          : (region == 3 ? fabsf(bpx) + fabsf(bpy) + fabsf(bpz) : 0.f);
+    Term r{d, fmaf(S, __logf(w.w), slogA), 0.f, 0.f, 0.f, (d + o) * 0x1p-21f};
+    if (GRAD) {
+        float inv = d > 0.f ? 1.f / d : 0.f;
+        float gx = dx * inv, gy = dy * inv, gz = dz * inv;
+        float k = S / w.w * inv_alpha;
+        if (metric) k *= inv_alpha;
+        float wgx = 0.f, wgy = 0.f, wgz = 0.f;   // grad w~ (Eq. 5)
+        if (region == 0) {
+            // grad phi1 = n x (v0 - v2) / |n|^2, grad phi2 = n x (v1 - v0) / |n|^2
+            float inn = 1.f / nn;
+            float g1x = dop(ny, -acz, nz, -acy) * inn, g1y = dop(nz, -acx, nx, -acz) * inn,
+                  g1z = dop(nx, -acy, ny, -acx) * inn;
+            float g2x = dop(ny, abz, nz, aby) * inn, g2y = dop(nz, abx, nx, abz) * inn,
+                  g2z = dop(nx, aby, ny, abx) * inn;
+            wgx = fmaf(w.wx, g1x, w.wy * g2x);
+            wgy = fmaf(w.wx, g1y, w.wy * g2y);
+            wgz = fmaf(w.wx, g1z, w.wy * g2z);
+        } else if (region != 4) {
+            float ee = dot3(ex, ey, ez, ex, ey, ez);
+            float dwdt = region == 1 ? w.wx : (region == 2 ? w.wy : w.wy - w.wx);
+            float c = dwdt / ee;
+            wgx = c * ex; wgy = c * ey; wgz = c * ez;
+        }
+        r.gx = fmaf(-k, wgx, gx);
+        r.gy = fmaf(-k, wgy, gy);
+        r.gz = fmaf(-k, wgz, gz);
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 over one class hierarchy
+// ---------------------------------------------------------------------------
+template <int CLS, bool GRAD, bool COUNT>
+__device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, float qx, float qy,
+                                         float qz, LSE &st, int &n_vis, int &n_far, int &n_leaf) {
+    const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
+    int node = 0;
+    while (node >= 0) {
+        float4 lo = T.lo[node];
+        float4 hi = T.hi[node];
+        float yx = fminf(fmaxf(qx, lo.x), hi.x);
+        float yy = fminf(fmaxf(qy, lo.y), hi.y);
+        float yz = fminf(fmaxf(qz, lo.z), hi.z);
+        float dx = qx - yx, dy = qy - yy, dz = qz - yz;
+        float D2 = dot3(dx, dy, dz, dx, dy, dz);
+        float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
+        float diag2 = dot3(ex, ey, ez, ex, ey, ez);
+        int esc = __float_as_int(lo.w);
+        int pay = __float_as_int(hi.w);
+        if (COUNT) ++n_vis;
+        if (diag2 < A.beta2 * D2) {
+            // far field at the closest box point y_B: weight n_B A^S (App. D)
+            float D = sqrtf(D2);
+            float inv = 1.f / D;
+            float lw = (pay < 0 ? 0.f : hi.w) + T.slogA;
+            lse_add<GRAD>(st, fmaf(-A.cons, D * 0x1p-22f, D), lw, dx * inv, dy * inv, dz * inv,
+                          A.alpha);
+            if (COUNT) ++n_far;
+            node = esc;
+        } else if (pay < 0) {
+            int slot = pay & 0x7fffffff;
+            Term t;
+            if (CLS == 0) {
+                t = point_term<GRAD>(lo, qx, qy, qz);
+            } else if (CLS == 1) {
+                t = edge_term<GRAD>(T.leaf[2 * slot], T.leaf[2 * slot + 1], qx, qy, qz, A.S,
+                                    T.slogA, A.inv_alpha, metric);
+            } else {
+                t = tri_term<GRAD>(T.leaf[3 * slot], T.leaf[3 * slot + 1], T.leaf[3 * slot + 2], qx,
+                                   qy, qz, A, T.slogA, metric);
+            }
+            lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
+            if (COUNT) ++n_leaf;
+            node = esc;
+        } else {
+            node = node + 1;
+        }
+    }
+}
+
+// Spread consecutive logical blocks over one XCD: hardware dispatches workgroup
+// i to XCD i % 8, so logical block = start(XCD) + i / 8 keeps each XCD's L2 on
+// a contiguous range of (Morton-ordered) queries.
+__device__ __forceinline__ int xcd_block(int i, int G) {
+    const int nx = 8;
+    int q = G / nx, r = G % nx;
+    int x = i % nx, k = i / nx;
+    return x * q + min(x, r) + k;
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void finalize(const EvalArgs &A, const LSE &st, int qi) {
+    float sum = st.s + st.sc;
+    float d, gx = 0.f, gy = 0.f, gz = 0.f;
+    if (!(sum > 0.f) && !(sum != sum)) {
+        d = INFINITY;   // empty scene: the empty sum
+    } else {
+        float corr;
+        if (A.flags & SD_ROOTLOG_F64) {
+            double s64 = (double)st.s + (double)st.sc;
+            double dd = (double)st.dref - ((double)st.lref + log(s64)) * (double)A.inv_alpha;
+            corr = (float)((double)st.dref - dd);
+            d = (float)dd;
+        } else {
+            corr = (st.lref + logf(sum)) * A.inv_alpha;
+            d = st.dref - corr;
+        }
+        if (!(A.flags & SD_NO_CONSERVATIVE_ROUNDING))
+            d -= A.margin_scale * (fabsf(st.dref) + fabsf(corr));
+        if (GRAD) {
+            float inv = 1.f / sum;
+            gx = (st.gx + st.cx) * inv;
+            gy = (st.gy + st.cy) * inv;
+            gz = (st.gz + st.cz) * inv;
+        }
+    }
+    A.d_out[qi] = d;
+    if (GRAD) {
+        A.g_out[3 * (int64_t)qi] = gx;
+        A.g_out[3 * (int64_t)qi + 1] = gy;
+        A.g_out[3 * (int64_t)qi + 2] = gz;
+    }
+}
+
+__device__ __forceinline__ void lse_init(LSE &st) {
+    st.dref = INFINITY; st.lref = 0.f; st.s = 0.f; st.sc = 0.f;
+    st.gx = st.gy = st.gz = st.cx = st.cy = st.cz = 0.f;
+}
+
+template <bool GRAD, bool COUNT, int MASK>
+__global__ void __launch_bounds__(kB) k_eval(EvalArgs A) {
+    int i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
+    if (i >= A.nq) return;
+    int qi = A.perm ? (int)A.perm[i] : i;
+    if ((unsigned)qi >= (unsigned)A.nq) return;
+    float qx = A.Q[3 * (int64_t)qi], qy = A.Q[3 * (int64_t)qi + 1], qz = A.Q[3 * (int64_t)qi + 2];
+    LSE st;
+    lse_init(st);
+    int nv = 0, nf = 0, nl = 0;
+    if (MASK & 1) traverse<0, GRAD, COUNT>(A.tree[0], A, qx, qy, qz, st, nv, nf, nl);
+    if (MASK & 2) traverse<1, GRAD, COUNT>(A.tree[1], A, qx, qy, qz, st, nv, nf, nl);
+    if (MASK & 4) traverse<2, GRAD, COUNT>(A.tree[2], A, qx, qy, qz, st, nv, nf, nl);
+    if (COUNT) {
+        A.counts[3 * (int64_t)qi] = nv;
+        A.counts[3 * (int64_t)qi + 1] = nf;
+        A.counts[3 * (int64_t)qi + 2] = nl;
+        return;
+    }
+    finalize<GRAD>(A, st, qi);
+}
+
+// all-pairs: tiles of leaf records in LDS, every primitive evaluated exactly
+template <int CLS, int K, bool GRAD>
+__device__ __forceinline__ void brute_class(const TreeView &T, int64_t n, const EvalArgs &A,
+                                            float4 *tile, float qx, float qy, float qz, LSE &st) {
+    const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
+    for (int64_t base = 0; base < n; base += kB) {
+        int cnt = (int)min<int64_t>(kB, n - base);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt * K; j += kB) tile[j] = T.leaf[base * K + j];
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            Term t;
+            if (CLS == 0) t = point_term<GRAD>(tile[j], qx, qy, qz);
+            else if (CLS == 1)
+                t = edge_term<GRAD>(tile[2 * j], tile[2 * j + 1], qx, qy, qz, A.S, T.slogA,
+                                    A.inv_alpha, metric);
+            else
+                t = tri_term<GRAD>(tile[3 * j], tile[3 * j + 1], tile[3 * j + 2], qx, qy, qz,
+                                   A, T.slogA, metric);
+            lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
+        }
+    }
+}
+
+template <bool GRAD>
+__global__ void __launch_bounds__(kB) k_brute(EvalArgs A, int64_t n0, int64_t n1, int64_t n2) {
+    __shared__ float4 tile[3 * kB];
+    int i = blockIdx.x * kB + threadIdx.x;
+    bool live = i < A.nq;
+    int qi = live ? i : 0;
+    float qx = A.Q[3 * (int64_t)qi], qy = A.Q[3 * (int64_t)qi + 1], qz = A.Q[3 * (int64_t)qi + 2];
+    LSE st;
+    lse_init(st);
+    brute_class<0, 1, GRAD>(A.tree[0], n0, A, tile, qx, qy, qz, st);
+    brute_class<1, 2, GRAD>(A.tree[1], n1, A, tile, qx, qy, qz, st);
+    brute_class<2, 3, GRAD>(A.tree[2], n2, A, tile, qx, qy, qz, st);
+    if (live) finalize<GRAD>(A, st, qi);
+}
+
+// ---------------------------------------------------------------------------
+// query ordering: 30-bit Morton keys in the (enlarged) scene box
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+    x &= 0x3ff;
+    x = (x | x << 16) & 0x030000ff;
+    x = (x | x << 8) & 0x0300f00f;
+    x = (x | x << 4) & 0x030c30c3;
+    x = (x | x << 2) & 0x09249249;
+    return x;
+}
+
+__global__ void __launch_bounds__(kB)
+k_query_keys(const float *__restrict__ Q, int64_t n, float lx, float ly, float lz, float sx,
+             float sy, float sz, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= n) return;
+    float u[3] = {(Q[3 * i] - lx) * sx, (Q[3 * i + 1] - ly) * sy, (Q[3 * i + 2] - lz) * sz};
+    uint32_t c = 0;
+    for (int a = 0; a < 3; ++a) {
+        float v = fminf(fmaxf(u[a], 0.f), 1.f);   // NaN -> 0
+        uint32_t q = (uint32_t)fminf(v * 1024.f, 1023.f);
+        c |= spread10(q) << (2 - a);
+    }
+    keys[i] = c;
+    vals[i] = (uint32_t)i;
+}
+
+template <bool GRAD, bool COUNT>
+void launch_eval(const EvalArgs &A, int mask, unsigned grid, hipStream_t s) {
+    switch (mask) {
+#define SD_CASE(m) \
+    case m: hipLaunchKernelGGL((k_eval<GRAD, COUNT, m>), dim3(grid), dim3(kB), 0, s, A); break;
+        SD_CASE(1) SD_CASE(2) SD_CASE(3) SD_CASE(4) SD_CASE(5) SD_CASE(6) SD_CASE(7)
+#undef SD_CASE
+        default: break;
+    }
+}
+
+}  // namespace
+
+// Morton order of the queries in the scene box enlarged by half its extent on
+// every side (queries outside clamp to the boundary cells).
+int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s) {
+    if (nq <= 0) return SD_OK;
+    uint64_t *keys, *keys2;
+    uint32_t *vals2;
+    void *temp;
+    size_t tb = radix_sort_temp_bytes(nq);
+    SD_HIP(hipMallocAsync((void **)&keys, nq * sizeof(uint64_t), s));
+    SD_HIP(hipMallocAsync((void **)&keys2, nq * sizeof(uint64_t), s));
+    SD_HIP(hipMallocAsync((void **)&vals2, nq * sizeof(uint32_t), s));
+    SD_HIP(hipMallocAsync(&temp, tb, s));
+    float ext[3], lo[3];
+    for (int a = 0; a < 3; ++a) {
+        float e = std::max(sc->box[3 + a] - sc->box[a], 1e-6f);
+        lo[a] = sc->box[a] - 0.5f * e;
+        ext[a] = 2.f * e;
+    }
+    unsigned grid = (unsigned)((nq + kB - 1) / kB);
+    hipLaunchKernelGGL(k_query_keys, dim3(grid), dim3(kB), 0, s, Q, nq, lo[0], lo[1], lo[2],
+                       1.f / ext[0], 1.f / ext[1], 1.f / ext[2], keys, perm);
+    SD_TRY(radix_sort_pairs(keys, perm, keys2, vals2, nq, 30, temp, s));
+    for (void *ptr : {(void *)keys, (void *)keys2, (void *)vals2, temp}) SD_HIP(hipFreeAsync(ptr, s));
+    return SD_OK;
+}
+
+int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, int64_t nq,
+                  const sd_params *p, float *d_out, float *g_out, int32_t *counts, bool brute,
+                  hipStream_t s) {
+    if (nq == 0) return SD_OK;
+    if (nq > (int64_t)0x7fffffff - kB) return fail(SD_EUNSUPPORTED, "more than 2^31 queries per call");
+    EvalArgs A;
+    memset(&A, 0, sizeof(A));
+    double alpha = p->alpha;
+    double S = alpha / std::max<double>(alpha, p->alpha_u);
+    for (int c = 0; c < 3; ++c) {
+        A.tree[c].lo = sc->lo[c];
+        A.tree[c].hi = sc->hi[c];
+        A.tree[c].leaf = sc->leaf[c];
+        A.tree[c].n_nodes = (int32_t)sc->n_nodes[c];
+        double sl = S * log(sc->A[c]);
+        float f = (float)sl;
+        if ((double)f < sl) f = nextafterf(f, INFINITY);   // far-field weights round up
+        A.tree[c].slogA = f;
+    }
+    A.tri_uniform = sc->n_tri_classes <= 1 ? 1 : 0;
+    memcpy(A.tri_coef, sc->tri_coef0, sizeof(A.tri_coef));
+    A.tri_table = sc->tri_table;
+    A.alpha = p->alpha;
+    A.inv_alpha = (float)(1.0 / alpha);
+    A.beta2 = p->beta * p->beta;
+    A.S = (float)S;
+    A.margin_scale = ldexpf(1.f, -22);
+    A.cons = (p->flags & SD_NO_CONSERVATIVE_ROUNDING) ? 0.f : 1.f;
+    A.flags = p->flags;
+    A.nq = (int32_t)nq;
+    A.Q = Q;
+    A.d_out = d_out;
+    A.g_out = g_out;
+    A.counts = counts;
+    int mask = (sc->n[0] > 0 ? 1 : 0) | (sc->n[1] > 0 ? 2 : 0) | (sc->n[2] > 0 ? 4 : 0);
+    unsigned grid = (unsigned)((nq + kB - 1) / kB);
+
+    if (mask == 0) {
+        // empty scene: the empty sum gives +inf and a zero gradient
+        if (counts) {
+            SD_HIP(hipMemsetAsync(counts, 0, 3 * nq * sizeof(int32_t), s));
+            return SD_OK;
+        }
+        brute = true;
+    }
+    if (brute) {
+        if (g_out)
+            hipLaunchKernelGGL(k_brute<true>, dim3(grid), dim3(kB), 0, s, A, sc->n[0], sc->n[1], sc->n[2]);
+        else
+            hipLaunchKernelGGL(k_brute<false>, dim3(grid), dim3(kB), 0, s, A, sc->n[0], sc->n[1], sc->n[2]);
+        SD_HIP(hipGetLastError());
+        return SD_OK;
+    }
+    uint32_t *perm = nullptr;
+    if (perm_in) {
+        A.perm = perm_in;
+    } else if (!(p->flags & SD_NO_QUERY_SORT) && nq >= 4096) {
+        SD_HIP(hipMallocAsync((void **)&perm, nq * sizeof(uint32_t), s));
+        SD_TRY(query_order(sc, Q, nq, perm, s));
+        A.perm = perm;
+    }
+    if (counts) {
+        if (g_out) launch_eval<true, true>(A, mask, grid, s);
+        else launch_eval<false, true>(A, mask, grid, s);
+    } else if (g_out) {
+        launch_eval<true, false>(A, mask, grid, s);
+    } else {
+        launch_eval<false, false>(A, mask, grid, s);
+    }
+    SD_HIP(hipGetLastError());
+    if (perm) SD_HIP(hipFreeAsync(perm, s));
+    return SD_OK;
+}
+
+}  // namespace sd

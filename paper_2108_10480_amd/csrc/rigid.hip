@@ -1,0 +1,113 @@
+// Rigidly moved query points and the adjoint of the smooth distance with
+// respect to the rigid transform and the body points.
+//
+// Forward:  x'_kj = R_k x_j + t_k for K transforms of m body points.
+// Adjoint:  with u_kj = gbar_kj * grad d(x'_kj)  (gbar = dL/dd upstream),
+//   tbar_k = sum_j u_kj,  Rbar_k = sum_j u_kj x_j^T,  xbar_j = sum_k R_k^T u_kj.
+// The reductions use a fixed order (per-thread strided sums, then an LDS tree),
+// so results are bitwise reproducible.
+#include "sd_internal.h"
+
+namespace sd {
+namespace {
+
+constexpr int kB = 256;
+
+__global__ void __launch_bounds__(kB)
+k_rigid_apply(const float *__restrict__ X, int64_t m, const float *__restrict__ R,
+              const float *__restrict__ t, int64_t K, float *__restrict__ Q) {
+    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= K * m) return;
+    int64_t k = i / m, j = i - k * m;
+    const float *r = R + 9 * k;
+    float x = X[3 * j], y = X[3 * j + 1], z = X[3 * j + 2];
+    Q[3 * i] = fmaf(r[0], x, fmaf(r[1], y, fmaf(r[2], z, t[3 * k])));
+    Q[3 * i + 1] = fmaf(r[3], x, fmaf(r[4], y, fmaf(r[5], z, t[3 * k + 1])));
+    Q[3 * i + 2] = fmaf(r[6], x, fmaf(r[7], y, fmaf(r[8], z, t[3 * k + 2])));
+}
+
+// one workgroup per transform: 12 sums (tbar 3, Rbar 9)
+__global__ void __launch_bounds__(kB)
+k_rigid_rt_bar(const float *__restrict__ X, int64_t m, const float *__restrict__ gbar,
+               const float *__restrict__ grad, float *__restrict__ Rbar, float *__restrict__ tbar) {
+    __shared__ float red[12][kB];
+    int64_t k = blockIdx.x;
+    float acc[12];
+#pragma unroll
+    for (int a = 0; a < 12; ++a) acc[a] = 0.f;
+    for (int64_t j = threadIdx.x; j < m; j += kB) {
+        int64_t i = k * m + j;
+        float g = gbar[i];
+        float u0 = g * grad[3 * i], u1 = g * grad[3 * i + 1], u2 = g * grad[3 * i + 2];
+        float x0 = X[3 * j], x1 = X[3 * j + 1], x2 = X[3 * j + 2];
+        acc[0] += u0; acc[1] += u1; acc[2] += u2;
+        acc[3] = fmaf(u0, x0, acc[3]); acc[4] = fmaf(u0, x1, acc[4]); acc[5] = fmaf(u0, x2, acc[5]);
+        acc[6] = fmaf(u1, x0, acc[6]); acc[7] = fmaf(u1, x1, acc[7]); acc[8] = fmaf(u1, x2, acc[8]);
+        acc[9] = fmaf(u2, x0, acc[9]); acc[10] = fmaf(u2, x1, acc[10]); acc[11] = fmaf(u2, x2, acc[11]);
+    }
+#pragma unroll
+    for (int a = 0; a < 12; ++a) red[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int w = kB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int a = 0; a < 12; ++a) red[a][threadIdx.x] += red[a][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) tbar[3 * k + threadIdx.x] = red[threadIdx.x][0];
+    else if (threadIdx.x < 12) Rbar[9 * k + threadIdx.x - 3] = red[threadIdx.x][0];
+}
+
+// one thread per body point
+__global__ void __launch_bounds__(kB)
+k_rigid_x_bar(const float *__restrict__ R, int64_t K, int64_t m, const float *__restrict__ gbar,
+              const float *__restrict__ grad, float *__restrict__ Xbar) {
+    int64_t j = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (j >= m) return;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int64_t k = 0; k < K; ++k) {
+        int64_t i = k * m + j;
+        float g = gbar[i];
+        float u0 = g * grad[3 * i], u1 = g * grad[3 * i + 1], u2 = g * grad[3 * i + 2];
+        const float *r = R + 9 * k;
+        a0 = fmaf(r[0], u0, fmaf(r[3], u1, fmaf(r[6], u2, a0)));
+        a1 = fmaf(r[1], u0, fmaf(r[4], u1, fmaf(r[7], u2, a1)));
+        a2 = fmaf(r[2], u0, fmaf(r[5], u1, fmaf(r[8], u2, a2)));
+    }
+    Xbar[3 * j] = a0;
+    Xbar[3 * j + 1] = a1;
+    Xbar[3 * j + 2] = a2;
+}
+
+}  // namespace
+}  // namespace sd
+
+extern "C" int sd_rigid_transform(const float *X, int64_t m, const float *R, const float *t,
+                                  int64_t K, float *Q_out, void *stream) {
+    if (m < 0 || K < 0) return sd::fail(SD_EINVAL, "sd_rigid_transform: negative size");
+    if (m == 0 || K == 0) return SD_OK;
+    if (!X || !R || !t || !Q_out) return sd::fail(SD_EINVAL, "sd_rigid_transform: null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t n = K * m;
+    hipLaunchKernelGGL(sd::k_rigid_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, m, R,
+                       t, K, Q_out);
+    SD_HIP(hipGetLastError());
+    return SD_OK;
+}
+
+extern "C" int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64_t K,
+                                const float *gbar, const float *grad, float *Rbar, float *tbar,
+                                float *Xbar, void *stream) {
+    if (m < 0 || K < 0) return sd::fail(SD_EINVAL, "sd_rigid_adjoint: negative size");
+    if (K == 0) return SD_OK;
+    if (!X || !R || !gbar || !grad || !Rbar || !tbar)
+        return sd::fail(SD_EINVAL, "sd_rigid_adjoint: null pointer");
+    if (K > 0x7fffffff) return sd::fail(SD_EUNSUPPORTED, "sd_rigid_adjoint: too many transforms");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(sd::k_rigid_rt_bar, dim3((unsigned)K), dim3(256), 0, s, X, m, gbar, grad, Rbar,
+                       tbar);
+    if (Xbar && m > 0)
+        hipLaunchKernelGGL(sd::k_rigid_x_bar, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, R, K,
+                           m, gbar, grad, Xbar);
+    SD_HIP(hipGetLastError());
+    return SD_OK;
+}

@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP translation units of libsd.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/sd.h"
+
+namespace sd {
+
+// ---------------------------------------------------------------------------
+// Error plumbing: every ABI entry point returns a code and records a message.
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define SD_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t _e = (call);                                                       \
+        if (_e != hipSuccess)                                                         \
+            return ::sd::fail(_e == hipErrorOutOfMemory ? SD_ENOMEM : SD_EHIP,        \
+                              std::string(#call) + ": " + hipGetErrorString(_e));     \
+    } while (0)
+
+#define SD_TRY(expr)                        \
+    do {                                    \
+        int _rc = (expr);                   \
+        if (_rc != SD_OK) return _rc;       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device layout of one class hierarchy (depth-first order, escape indices).
+//
+//   node_lo[i] = (min.x, min.y, min.z, bits: escape index, -1 = end)
+//   node_hi[i] = (max.x, max.y, max.z, payload)
+//   payload: internal node -> float log(n_B) rounded up (n_B = leaves below);
+//            leaf           -> int bits 0x80000000 | leaf slot.
+//   The left child of internal node i is i + 1; its right child is the left
+//   child's escape index.
+//
+// Leaf records (leaf slot k = k-th leaf in depth-first order):
+//   points:    none (the leaf box is the point)
+//   edges:     2 x float4 (v0.xyz, 1/N0), (v1.xyz, 1/N1)
+//   triangles: 3 x float4 (v0.xyz, iv), (v1.xyz, ie), (v2.xyz, ic)
+// ---------------------------------------------------------------------------
+struct TreeView {
+    const float4 *lo;
+    const float4 *hi;
+    const float4 *leaf;   // edges / triangles only
+    int32_t n_nodes;
+    float slogA;          // S log A of the class, filled per evaluation
+};
+
+struct EvalArgs {
+    TreeView tree[3];
+    // Triangle weights (App. C.3) as degree-7 Bernstein coefficients per
+    // valence class, 36 per class; a single class is passed by value.
+    float tri_coef[36];
+    const float *tri_table;   // n_classes x 36 (class id in the leaf record)
+    int32_t tri_uniform;      // 1: every triangle uses tri_coef
+    float alpha, inv_alpha, beta2, S;
+    float margin_scale;   // final rounding margin: 2^-22 (|d*| + |log-sum term|)
+    float cons;           // 1: each term enters at its rounded-down distance (default)
+    uint32_t flags;
+    int32_t nq;
+    const float *Q;
+    const uint32_t *perm;  // optional query order (nullptr = identity)
+    float *d_out;
+    float *g_out;          // nullptr for value only
+    int32_t *counts;       // nullptr unless counting
+};
+
+// Host-side weight constants (weights.cpp)
+int triangle_basis_f64(double out[3][64]);
+double triangle_weight_min_f64(int v, int e);   // min over the barycentric triangle
+void triangle_bernstein(int v, int e, float out[36]);
+
+// Sorting and scans (sort.hip)
+size_t radix_sort_temp_bytes(int64_t n);
+// Stable ascending sort of (key, val) pairs by the low `bits` bits of key.
+int radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_tmp, uint32_t *vals_tmp,
+                     int64_t n, int bits, void *temp, hipStream_t s);
+int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, void *temp,
+                       hipStream_t s);
+
+}  // namespace sd
+
+// Opaque scene handle
+struct sd_scene {
+    int64_t n[3] = {0, 0, 0};
+    int64_t n_nodes[3] = {0, 0, 0};
+    float4 *lo[3] = {nullptr, nullptr, nullptr};
+    float4 *hi[3] = {nullptr, nullptr, nullptr};
+    float4 *leaf[3] = {nullptr, nullptr, nullptr};
+    int32_t *prim_id[3] = {nullptr, nullptr, nullptr};   // leaf slot -> original id
+    float *wt[3] = {nullptr, nullptr, nullptr};          // original order weight data
+    double A[3] = {1.0, 1.0, 1.0};
+    double A_T_literal = 1.0;
+    double diam_max = 0.0;
+    float box[6] = {0, 0, 0, 0, 0, 0};                    // union of class boxes
+    int32_t n_tri_classes = 0;
+    float *tri_table = nullptr;                           // n_tri_classes x 36 Bernstein coefs
+    float tri_coef0[36];                                  // host copy of class 0
+    int64_t device_bytes = 0;
+    int device = 0;
+};
+
+namespace sd {
+// Query Morton ordering used by the evaluation (eval.hip)
+int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s);
+int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, int64_t nq,
+                  const sd_params *p, float *d_out, float *g_out, int32_t *counts, bool brute,
+                  hipStream_t s);
+}  // namespace sd

@@ -181,10 +181,10 @@ def random_points(n, seed, scale=1.0):
     return Scene(V=V, P=_i32(np.arange(n)), name=f"rand_points_{n}")
 
 
-def random_polyline(n_seg, seed, closed=False):
+def random_polyline(n_seg, seed, closed=False, step=0.3):
     """A random-walk polyline (interior vertices have edge valence 2)."""
     rng = np.random.default_rng(seed)
-    steps = rng.normal(0.0, 0.3, (n_seg + 1, 3))
+    steps = rng.normal(0.0, step, (n_seg + 1, 3))
     V = np.cumsum(steps, axis=0)
     nv = n_seg if closed else n_seg + 1
     V = V[:nv]

@@ -1,0 +1,315 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs, element by element.
+
+* beta = 0 and the all-pairs kernel against the oracle's brute force (Eq. 3,
+  Eq. 4 over every primitive);
+* beta > 0 against the oracle's Alg. 1 on the hierarchy the library built
+  (exported), excluding only queries whose opening decision is a rounding tie
+  (relative margin below 1e-5; their count is bounded);
+* conservativeness d <= d_min (App. A, Sec. 3.5) on every query;
+* edge cases: empty scene, single primitive, ragged sizes, NaN and on-surface
+  queries, degenerate triangles, invalid arguments.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import (CUT_TIE, O, api, compare, cuda, floor_of, oracle_scene, oracle_trees,
+                              require_gpu, scenes, torch)
+
+pytestmark = pytest.mark.gpu
+
+
+NOCONS = api.SD_NO_CONSERVATIVE_ROUNDING
+
+
+def _run(scene, Q, alpha, beta, alpha_u=0.0, flags=0):
+    """Arithmetic parity runs skip the final conservative rounding (a
+    deliberate downward shift checked separately by _check_conservative)."""
+    d, g = api.sd_eval_grad(scene, cuda(Q), alpha, beta, alpha_u, flags | NOCONS)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), g.cpu().numpy()
+
+
+def _check_conservative(scene, Q, alpha, beta, dmin, d_plain, alpha_u=0.0, flags=0, brute=False):
+    """Default evaluation: d <= d_min on every query, and the rounding shift
+    below the plain result is small (bounded by 2^-19 of the magnitudes)."""
+    if brute:
+        dc = api.sd_eval_brute(scene, cuda(Q), alpha, alpha_u, flags, grad=False)
+    else:
+        dc = api.sd_eval(scene, cuda(Q), alpha, beta, alpha_u, flags)
+    torch.cuda.synchronize()
+    dc = dc.cpu().numpy().astype(np.float64)
+    bad = dc > dmin
+    assert not bad.any(), f"conservativeness violated on {bad.sum()} queries"
+    shift = np.asarray(d_plain, np.float64) - dc
+    fin = np.isfinite(dc)
+    assert np.all(shift[fin] >= 0)
+    scale = np.abs(dc) + dmin + np.abs(np.asarray(d_plain, np.float64)) + 3.0
+    assert np.all(shift[fin] <= 2.0 ** -19 * scale[fin])
+
+
+def _mixed_scene(seed=40):
+    ico = scenes.bumpy_icosphere(level=3, seed=seed)
+    pl = scenes.random_polyline(300, seed=seed + 1, step=0.05)
+    rng = np.random.default_rng(seed + 2)
+    pts = rng.uniform(-1.2, 1.2, (700, 3)).astype(np.float32)
+    nV1, nV2 = len(ico.V), len(pl.V)
+    V = np.concatenate([ico.V, pl.V * np.float32(0.3) + np.float32(0.5), pts])
+    return scenes.Scene(V=V, P=np.arange(nV1 + nV2, nV1 + nV2 + 700, dtype=np.int32),
+                        E=(pl.E + nV1).astype(np.int32), T=ico.T, name="mixed")
+
+
+CASES = {
+    "points": lambda: scenes.point_sphere(2000, 10000)[0],
+    "polyline": lambda: scenes.random_polyline(3000, seed=7),
+    "icosphere_l4": lambda: scenes.bumpy_icosphere(level=4, seed=2),
+    "mixed": _mixed_scene,
+}
+
+
+def _queries(sc, n, seed):
+    if sc.T is not None and sc.P is None and sc.E is None:
+        return scenes.icosphere_queries(sc, n, seed_box=seed, seed_surf=seed + 1)
+    lo, hi = scenes.scene_aabb(sc)
+    c, h = 0.5 * (lo + hi), 0.75 * (hi - lo)
+    return scenes.uniform_queries(n, seed, c - h, c + h)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    require_gpu()
+    sc = CASES[request.param]()
+    scene = api.upload_scene(sc)
+    return request.param, sc, scene, oracle_scene(sc), oracle_trees(scene)
+
+
+@pytest.mark.parametrize("alpha", [50.0, 500.0])
+def test_brute_kernel_matches_oracle(case, alpha):
+    name, sc, scene, osc, _ = case
+    Q = _queries(sc, 3001, seed=11)        # ragged: 3001 = 11 * 256 + 185
+    d, g = api.sd_eval_brute(scene, cuda(Q), alpha, flags=NOCONS)
+    torch.cuda.synchronize()
+    d, g = d.cpu().numpy(), g.cpu().numpy()
+    dr, gr, dm = O.brute(osc, Q.astype(np.float64), alpha)
+    compare(d, g, dr, gr, floor_of(sc), what=f"{name} brute", dmin=dm)
+    _check_conservative(scene, Q, alpha, 0.0, dm, d, brute=True)
+
+
+def test_beta_zero_traversal_matches_oracle_brute(case):
+    name, sc, scene, osc, _ = case
+    Q = _queries(sc, 2000, seed=12)
+    d, g = _run(scene, Q, 80.0, 0.0)
+    dr, gr, dm = O.brute(osc, Q.astype(np.float64), 80.0)
+    compare(d, g, dr, gr, floor_of(sc), what=f"{name} beta=0", dmin=dm)
+    _check_conservative(scene, Q, 80.0, 0.0, dm, d)
+
+
+@pytest.mark.parametrize("alpha,beta,alpha_u", [(50.0, 0.5, 0.0), (500.0, 0.5, 0.0),
+                                                (100.0, 1.0, 0.0), (50.0, 0.5, 300.0)])
+def test_barnes_hut_matches_oracle_on_exported_tree(case, alpha, beta, alpha_u):
+    name, sc, scene, osc, trees = case
+    Q = _queries(sc, 10000, seed=13)
+    d, g = _run(scene, Q, alpha, beta, alpha_u)
+    dr, gr, st = O.barnes_hut(osc, trees, Q.astype(np.float64), alpha, beta, alpha_u=alpha_u)
+    ok = st[:, 0] > CUT_TIE
+    assert ok.mean() > 0.99, f"too many cut ties: {(~ok).sum()}"
+    dm = O.dmin(osc, Q.astype(np.float64))
+    compare(d, g, dr, gr, floor_of(sc), mask=ok, what=f"{name} BH a={alpha} b={beta}", dmin=dm)
+    _check_conservative(scene, Q, alpha, beta, dm, d, alpha_u=alpha_u)
+
+
+def test_paper_metric_and_rootlog_flags(case):
+    name, sc, scene, osc, trees = case
+    Q = _queries(sc, 3000, seed=14)
+    alpha = 60.0
+    d, g = _run(scene, Q, alpha, 0.5, flags=api.SD_GRAD_PAPER_METRIC | api.SD_ROOTLOG_F64)
+    dr, gr, st = O.barnes_hut(osc, trees, Q.astype(np.float64), alpha, 0.5, metric_r2=True)
+    ok = st[:, 0] > CUT_TIE
+    compare(d, g, dr, gr, floor_of(sc), mask=ok, what=f"{name} metric+rootlog",
+            dmin=O.dmin(osc, Q.astype(np.float64)))
+
+
+def test_counters_are_consistent(case):
+    name, sc, scene, osc, trees = case
+    Q = _queries(sc, 2000, seed=15)
+    c = api.sd_eval_counters(scene, cuda(Q), 50.0, 0.5).cpu().numpy()
+    _, _, st = O.barnes_hut(osc, trees, Q.astype(np.float64), 50.0, 0.5)
+    ok = st[:, 0] > CUT_TIE
+    np.testing.assert_array_equal(c[ok, 0], st[ok, 1])   # nodes visited
+    np.testing.assert_array_equal(c[ok, 1], st[ok, 2])   # far-field terms
+    np.testing.assert_array_equal(c[ok, 2], st[ok, 3])   # exact leaves
+
+
+def test_exported_hierarchy_is_valid(case):
+    """Every primitive sits in exactly one leaf, children boxes nest in their
+    parent, and the depth-first order has each left child right after its
+    parent."""
+    name, sc, scene, osc, trees = case
+    counts = sc.counts()
+    for c in range(3):
+        t = api.sd_export_bvh(scene, c)
+        if counts[c] == 0:
+            assert t is None
+            continue
+        box, left, right, prim = t
+        n = counts[c]
+        assert len(left) == 2 * n - 1
+        leaves = prim[left < 0]
+        assert np.array_equal(np.sort(leaves), np.arange(n))
+        internal = np.where(left >= 0)[0]
+        assert np.all(left[internal] == internal + 1)
+        for ch in (left[internal], right[internal]):
+            assert np.all(box[ch, :3] >= box[internal, :3]) and np.all(box[ch, 3:] <= box[internal, 3:])
+
+
+def test_weight_data_matches_oracle_valences(case):
+    name, sc, scene, osc, trees = case
+    info = scene.info()
+    if sc.E is not None:
+        w = api.sd_export_weights(scene, 1)
+        n0, n1, amax = O.edge_valences(sc.E.astype(np.int64), len(sc.V))
+        np.testing.assert_array_equal(w[:, 0], (1.0 / n0).astype(np.float32))
+        np.testing.assert_array_equal(w[:, 1], (1.0 / n1).astype(np.float32))
+        assert info["A"][1] == amax == osc.A_E
+    if sc.T is not None:
+        w = api.sd_export_weights(scene, 2)
+        v, e = O.triangle_valences(sc.T.astype(np.int64), len(sc.V))
+        np.testing.assert_array_equal(w[:, 0], (1.0 / v).astype(np.float32))
+        np.testing.assert_array_equal(w[:, 1], (1.0 / e).astype(np.float32))
+        assert abs(info["A"][2] - osc.A_T) < 1e-9 * osc.A_T
+        assert info["A_T_literal"] == osc.A_T_literal
+
+
+def test_deterministic(case):
+    name, sc, scene, _, _ = case
+    Q = cuda(_queries(sc, 5000, seed=16))
+    a = api.sd_eval_grad(scene, Q, 50.0, 0.5)
+    b = api.sd_eval_grad(scene, Q, 50.0, 0.5)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_value_only_equals_value_of_grad(case):
+    name, sc, scene, _, _ = case
+    Q = cuda(_queries(sc, 3000, seed=17))
+    d1 = api.sd_eval(scene, Q, 50.0, 0.5)
+    d2, _ = api.sd_eval_grad(scene, Q, 50.0, 0.5)
+    torch.cuda.synchronize()
+    assert torch.equal(d1, d2)
+
+
+def test_query_sorting_does_not_change_results(case):
+    name, sc, scene, _, _ = case
+    Q = cuda(_queries(sc, 6000, seed=18))
+    a = api.sd_eval_grad(scene, Q, 50.0, 0.5)
+    b = api.sd_eval_grad(scene, Q, 50.0, 0.5, flags=api.SD_NO_QUERY_SORT)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+# --------------------------------------------------------------------------
+# edge cases
+# --------------------------------------------------------------------------
+def test_literal_scale_flag():
+    require_gpu()
+    sc = scenes.bumpy_icosphere(level=2, seed=3)
+    scene = api.upload_scene(sc, flags=api.SD_BUILD_A_PAPER_LITERAL)
+    osc = oracle_scene(sc, a_literal=True)
+    assert scene.info()["A"][2] == 6.0 == osc.A_T
+    Q = _queries(sc, 1000, seed=19)
+    d, g = _run(scene, Q, 40.0, 0.0)
+    dr, gr, dm = O.brute(osc, Q.astype(np.float64), 40.0)
+    compare(d, g, dr, gr, floor_of(sc), what="literal A", dmin=dm)
+
+
+def test_empty_scene_and_empty_queries():
+    require_gpu()
+    V = cuda(np.zeros((4, 3), np.float32))
+    scene = api.sd_build_bvh(V)
+    Q = cuda(np.random.default_rng(0).uniform(-1, 1, (300, 3)).astype(np.float32))
+    d, g = api.sd_eval_grad(scene, Q, 10.0, 0.5)
+    torch.cuda.synchronize()
+    assert torch.all(torch.isinf(d)) and torch.all(d > 0) and torch.all(g == 0)
+    d = api.sd_eval(scene, Q, 10.0, 0.5)
+    assert torch.all(torch.isinf(d))
+    c = api.sd_eval_counters(scene, Q, 10.0, 0.5)
+    assert torch.all(c == 0)
+    sc2 = api.upload_scene(scenes.point_sphere(50, 1)[0])
+    d, g = api.sd_eval_grad(sc2, cuda(np.zeros((0, 3), np.float32)), 10.0, 0.5)
+    assert d.numel() == 0
+
+
+@pytest.mark.parametrize("kind", ["point", "edge", "triangle"])
+def test_single_primitive(kind):
+    require_gpu()
+    rng = np.random.default_rng(5)
+    V = rng.uniform(-1, 1, (3, 3)).astype(np.float32)
+    sc = scenes.Scene(V=V, P=np.array([1], np.int32) if kind == "point" else None,
+                      E=np.array([[0, 2]], np.int32) if kind == "edge" else None,
+                      T=np.array([[0, 1, 2]], np.int32) if kind == "triangle" else None)
+    scene = api.upload_scene(sc)
+    Q = rng.uniform(-2, 2, (777, 3)).astype(np.float32)
+    Q[0] = V[1] if kind != "edge" else V[0]      # a query on the primitive
+    for beta in (0.0, 0.5):
+        d, g = _run(scene, Q, 30.0, beta)
+        dr, gr, _ = O.barnes_hut(oracle_scene(sc), oracle_trees(scene), Q.astype(np.float64), 30.0, beta)
+        compare(d, g, dr, gr, 1e-3, what=f"single {kind} beta={beta}")
+    d, g = _run(scene, Q, 30.0, 0.0)
+    assert d[0] <= 0 and np.all(g[0] == 0)       # Eq. 11: zero gradient at d = 0
+
+
+def test_nan_query_gives_nan():
+    require_gpu()
+    sc = scenes.bumpy_icosphere(level=2, seed=3)
+    scene = api.upload_scene(sc)
+    Q = np.zeros((5, 3), np.float32)
+    Q[2, 1] = np.nan
+    d, g = _run(scene, Q, 20.0, 0.5)
+    assert np.isnan(d[2]) and np.all(np.isfinite(np.delete(d, 2)))
+
+
+def test_degenerate_triangles():
+    require_gpu()
+    V = np.array([[0, 0, 0], [1, 1, 1], [2, 2, 2], [0, 1, 0], [1, 0, 0], [0, 0, 1]], np.float32)
+    T = np.array([[0, 1, 2], [0, 4, 3], [0, 5, 4], [0, 3, 5], [3, 4, 5], [1, 1, 2]], np.int32)
+    sc = scenes.Scene(V=V, T=T)
+    scene = api.upload_scene(sc)
+    Q = np.random.default_rng(6).uniform(-1, 3, (1000, 3)).astype(np.float32)
+    d, g = _run(scene, Q, 25.0, 0.0)
+    osc = oracle_scene(sc)
+    dr, gr, dm = O.brute(osc, Q.astype(np.float64), 25.0)
+    compare(d, g, dr, gr, 1e-3, what="degenerate", dmin=dm)
+    _check_conservative(scene, Q, 25.0, 0.0, dm, d)
+
+
+def test_invalid_arguments_raise():
+    require_gpu()
+    V = cuda(np.zeros((3, 3), np.float32))
+    with pytest.raises(api.SdError) as e:
+        api.sd_build_bvh(V, T=cuda(np.array([[0, 1, 5]], np.int32)))
+    assert e.value.code == -1 and "index" in str(e.value)
+    with pytest.raises(api.SdError):
+        api.sd_build_bvh(V, E=cuda(np.array([[0, -1]], np.int32)))
+    sc = api.upload_scene(scenes.point_sphere(20, 1)[0])
+    Q = cuda(np.zeros((4, 3), np.float32))
+    for bad in (dict(alpha=0.0), dict(alpha=-1.0), dict(alpha=float("nan")), dict(alpha=1.0, beta=-0.1),
+                dict(alpha=1.0, alpha_u=-1.0)):
+        with pytest.raises(api.SdError):
+            api.sd_eval(sc, Q, **bad)
+
+
+def test_huge_alpha_is_finite():
+    """Large alpha d never overflows: the running maximum is factored out
+    (the paper's FP64 sums would return inf far from the data)."""
+    require_gpu()
+    sc = scenes.point_sphere(500, 1)[0]
+    scene = api.upload_scene(sc)
+    Q = np.array([[40.0, 0, 0], [0, -30, 5], [0.1, 0.2, 0.3]], np.float32)
+    dm = O.dmin(oracle_scene(sc), Q.astype(np.float64))
+    for beta in (0.0, 0.5):
+        d, g = _run(scene, Q, 5e4, beta)
+        assert np.all(np.isfinite(d)) and np.all(np.isfinite(g))
+        _check_conservative(scene, Q, 5e4, beta, dm, d)
+        # App. A with unit weights: d_min - log|F|/alpha <= d (brute force, beta = 0);
+        # the Barnes-Hut bound divides d_min by (1 + beta)
+        assert np.all(d >= dm / (1 + beta) - np.log(500) / 5e4 - 1e-5)

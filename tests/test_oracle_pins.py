@@ -621,3 +621,26 @@ def test_rigid_adjoint_matches_finite_differences(oracle_mod):
             e = np.zeros_like(Xd); e[j, a] = h
             fd = (loss(Xd + e, Rd, td) - loss(Xd - e, Rd, td)) / (2 * h)
             assert abs(fd - Xb[j, a]) < 1e-6 * max(1, abs(fd))
+
+
+def test_degenerate_triangle_is_its_longest_edge(oracle_mod):
+    """Zero-area triangles (the paper is silent): the distance is the exact
+    distance to the collinear vertices' hull, i.e. to the longest edge, and
+    the closest point's barycentrics come from that edge."""
+    O = oracle_mod
+    V = np.array([[0, 0, 0], [1, 1, 1], [3, 3, 3]], np.float32)
+    rng = np.random.default_rng(35)
+    for q in rng.uniform(-1, 4, (50, 3)):
+        r = O.closest(2, V.reshape(-1), q)
+        s = O.closest(1, np.concatenate([V[0], V[2]]), q)
+        assert abs(r["d"] - s["d"]) < 1e-12
+        # longest edge is (v2, v0): phi = (0, 1 - t) with t measured from v2
+        assert r["phi"][0] == 0.0
+        x = (1 - r["phi"].sum()) * V[0].astype(float) + r["phi"][1] * V[2].astype(float)
+        np.testing.assert_allclose(x, r["c"], atol=1e-12)
+    # a triangle with a repeated vertex
+    V2 = np.array([[1, 1, 1], [1, 1, 1], [2, 2, 2]], np.float32)
+    q = np.array([1.5, 1.7, 1.2])
+    r = O.closest(2, V2.reshape(-1), q)
+    s = O.closest(1, np.concatenate([V2[0], V2[2]]), q)
+    assert abs(r["d"] - s["d"]) < 1e-12
