@@ -59,7 +59,18 @@ def main():
     ap.add_argument("--nq", type=int, default=1_000_000)
     ap.add_argument("--cpu-sample", type=int, default=250000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run 3 plain device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        x = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
               "(queries shard with no communication; see the design notes)", file=sys.stderr)
@@ -122,6 +133,21 @@ def main():
     eval_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))   # the traversal kernel alone
     qps = n / (ms_step * 1e-3)
 
+    # the same step visiting every node of Alg. 1's cut (no negligible-subtree skipping)
+    e2 = torch.cuda.Event(enable_timing=True)
+    e3 = torch.cuda.Event(enable_timing=True)
+    e2.record(s)
+    for k in range(args.steps):
+        api.sd_query_order(scene, Qd, out=perm)
+        api.sd_eval_grad_ordered(scene, Qd, perm, args.alpha, args.beta, flags=api.SD_NO_PRUNE,
+                                 out=d, grad_out=g)
+    e3.record(s)
+    torch.cuda.synchronize()
+    ms_step_noprune = e2.elapsed_time(e3) / args.steps
+    cnt_np = api.sd_eval_counters(scene, Qd, args.alpha, args.beta, flags=api.SD_NO_PRUNE).double()
+    api.sd_query_order(scene, Qd, out=perm)
+    api.sd_eval_grad_ordered(scene, Qd, perm, args.alpha, args.beta, out=d, grad_out=g)
+
     # work counters on the same inputs -> algorithmic bytes
     cnt = api.sd_eval_counters(scene, Qd, args.alpha, args.beta).double()
     nodes, far, leaves = [float(x) for x in cnt.mean(0).cpu()]
@@ -168,6 +194,9 @@ def main():
         "stages_ms": {"query_order": order_ms, "traversal": eval_ms, "build": min(builds)},
         "work_per_query": {"nodes": nodes, "far_terms": far, "leaves": leaves,
                            "p99_nodes": p99[0], "p99_far": p99[1], "p99_leaves": p99[2]},
+        "no_prune": {"value": n / (ms_step_noprune * 1e-3), "ms_per_step": ms_step_noprune,
+                     "nodes": float(cnt_np[:, 0].mean()), "far_terms": float(cnt_np[:, 1].mean()),
+                     "leaves": float(cnt_np[:, 2].mean())},
     }
 
     if not args.no_cpu_baseline:

@@ -53,7 +53,10 @@ enum {
                                        default is the exact derivative of Eq. 3                 */
 #define SD_ROOTLOG_F64       0x2u   /* final logarithm of the accumulated sum in FP64 (Alg. 2)   */
 #define SD_NO_QUERY_SORT     0x4u   /* evaluate queries in input order (no Morton reordering)    */
-#define SD_NO_CONSERVATIVE_ROUNDING 0x8u /* skip the final downward rounding margin             */
+#define SD_NO_CONSERVATIVE_ROUNDING 0x8u /* skip the downward rounding of terms and result     */
+#define SD_NO_PRUNE          0x10u  /* visit every node Alg. 1 visits, even subtrees whose terms
+                                       are all below exp(-64) of the running maximum (by default
+                                       those are skipped: they cannot change an FP32 result)   */
 
 typedef struct sd_params {
     float alpha;     /* accuracy / smoothness, > 0 (Eq. 3)                                   */

@@ -22,6 +22,7 @@ SD_GRAD_PAPER_METRIC = 0x1
 SD_ROOTLOG_F64 = 0x2
 SD_NO_QUERY_SORT = 0x4
 SD_NO_CONSERVATIVE_ROUNDING = 0x8
+SD_NO_PRUNE = 0x10
 
 _c_p = ctypes.c_void_p
 _i64 = ctypes.c_int64

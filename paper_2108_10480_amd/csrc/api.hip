@@ -82,8 +82,9 @@ int sd_build_bvh(const float *V, int64_t nV, const int32_t *P, int64_t nP, const
 int sd_free_scene(sd_scene *sc) {
     if (!sc) return SD_OK;
     for (int c = 0; c < 3; ++c) {
-        for (void *p : {(void *)sc->lo[c], (void *)sc->hi[c], (void *)sc->leaf[c],
-                        (void *)sc->prim_id[c], (void *)sc->wt[c]})
+        // hi[c] points into the interleaved lo[c] allocation
+        for (void *p : {(void *)sc->lo[c], (void *)sc->leaf[c], (void *)sc->prim_id[c],
+                        (void *)sc->wt[c]})
             if (p) (void)hipFree(p);
     }
     if (sc->tri_table) (void)hipFree(sc->tri_table);
@@ -157,13 +158,16 @@ int sd_export_bvh(const sd_scene *sc, int cls, float *box_host, int32_t *left_ho
     if (!box_host || !left_host || !right_host || !prim_host)
         return fail(SD_EINVAL, "sd_export_bvh: null output");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<float4> lo(nn), hi(nn);
+    std::vector<float4> rec(2 * nn), lo(nn), hi(nn);
     std::vector<int32_t> pid(sc->n[cls]);
-    SD_HIP(hipMemcpyAsync(lo.data(), sc->lo[cls], nn * sizeof(float4), hipMemcpyDeviceToHost, s));
-    SD_HIP(hipMemcpyAsync(hi.data(), sc->hi[cls], nn * sizeof(float4), hipMemcpyDeviceToHost, s));
+    SD_HIP(hipMemcpyAsync(rec.data(), sc->lo[cls], 2 * nn * sizeof(float4), hipMemcpyDeviceToHost, s));
     SD_HIP(hipMemcpyAsync(pid.data(), sc->prim_id[cls], sc->n[cls] * sizeof(int32_t),
                           hipMemcpyDeviceToHost, s));
     SD_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < nn; ++i) {
+        lo[i] = rec[2 * i];
+        hi[i] = rec[2 * i + 1];
+    }
     for (int64_t i = 0; i < nn; ++i) {
         box_host[6 * i] = lo[i].x; box_host[6 * i + 1] = lo[i].y; box_host[6 * i + 2] = lo[i].z;
         box_host[6 * i + 3] = hi[i].x; box_host[6 * i + 4] = hi[i].y; box_host[6 * i + 5] = hi[i].z;

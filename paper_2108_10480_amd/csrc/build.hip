@@ -225,8 +225,8 @@ k_dfs_layout(int64_t n, const int32_t *__restrict__ left, const int32_t *__restr
     float4 a = blo[x], b = bhi[x];
     a.w = __int_as_float(esc32);
     b.w = leaf ? __int_as_float((int32_t)(0x80000000u | (uint32_t)l)) : log_count_up(cnt);
-    out_lo[pos] = a;
-    out_hi[pos] = b;
+    out_lo[2 * pos] = a;   // records interleaved: lo, hi of a node share a cache line
+    out_hi[2 * pos] = b;
 }
 
 // ---------------------------------------------------------------------------
@@ -406,8 +406,8 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
     hipLaunchKernelGGL(k_refit, dim3(grid_for(n)), dim3(kB), 0, s, plo, phi, vals, n, left, right,
                        parent, flag, blo, bhi);
     int64_t acc = 0;
-    SD_TRY(dalloc(&sc->lo[cls], nn, s, &acc));
-    SD_TRY(dalloc(&sc->hi[cls], nn, s, &acc));
+    SD_TRY(dalloc(&sc->lo[cls], 2 * nn, s, &acc));
+    sc->hi[cls] = sc->lo[cls] + 1;
     SD_TRY(dalloc(&sc->prim_id[cls], n, s, &acc));
     hipLaunchKernelGGL(k_dfs_layout, dim3(grid_for(nn)), dim3(kB), 0, s, n, left, first, last,
                        parent, blo, bhi, sc->lo[cls], sc->hi[cls]);
@@ -539,6 +539,7 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
             A = std::max(A, 1.0 / wmin);
         }
         sc->n_tri_classes = ncls;
+        for (float b : table) sc->tri_wmax = std::max(sc->tri_wmax, (double)b);
         sc->A[2] = (flags & SD_BUILD_A_PAPER_LITERAL) ? sc->A_T_literal : A;
         memcpy(sc->tri_coef0, table.data(), sizeof(sc->tri_coef0));
         int32_t *lut_dev, *tri_cls;

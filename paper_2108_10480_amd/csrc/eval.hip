@@ -10,10 +10,11 @@
 //
 // Online log-sum-exp state per lane: the distance d* and log-weight l* of the
 // largest term so far, the sum s of exp(L_i - L*) and the gradient numerator
-// G, both with Neumaier compensation.  Exponents are formed as
+// G, both with Kahan compensation.  Exponents are formed as
 // alpha (d* - d_i) + (l_i - l*), so large alpha d never overflows and no
 // precision is lost to the magnitude of alpha d.  d = d* - (l* + log s)/alpha.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -37,17 +38,29 @@ __device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, fl
     return fmaf(ax, bx, fmaf(ay, by, az * bz));
 }
 
+// Hardware square root and reciprocal (1 ulp) instead of the correctly rounded
+// multi-instruction sequences; the error bounds below allow for them.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * frcp(b); }
+
 struct LSE {
     float dref, lref, s, sc;
     float gx, gy, gz, cx, cy, cz;
 };
 
-__device__ __forceinline__ void neumaier(float &s, float &c, float x) {
-    float t = s + x;
-    bool big = fabsf(s) >= fabsf(x);
-    float a = big ? s : x, b = big ? x : s;
-    c += (a - t) + b;
+// Compensated (Kahan) accumulation: the running sum is s + c, where c carries
+// the low-order part lost by the last addition.  Four FLOPs per term.
+__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
+    float y = x + c;
+    float t = s + y;
+    c = y - (t - s);
     s = t;
+}
+
+// clamp(q, lo, hi) in one v_med3_f32 (lo <= hi for every box)
+__device__ __forceinline__ float clampf(float q, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(q, lo, hi);
 }
 
 template <bool GRAD>
@@ -56,23 +69,23 @@ __device__ __forceinline__ void lse_add(LSE &st, float d, float lw, float gx, fl
     float t = fmaf(alpha, st.dref - d, lw - st.lref);   // L_i - L*
     if (t <= 0.f) {
         float e = __expf(t);
-        neumaier(st.s, st.sc, e);
+        kahan_add(st.s, st.sc, e);
         if (GRAD) {
-            neumaier(st.gx, st.cx, e * gx);
-            neumaier(st.gy, st.cy, e * gy);
-            neumaier(st.gz, st.cz, e * gz);
+            kahan_add(st.gx, st.cx, e * gx);
+            kahan_add(st.gy, st.cy, e * gy);
+            kahan_add(st.gz, st.cz, e * gz);
         }
     } else {
         float e = __expf(-t);
         st.s *= e;
         st.sc *= e;
-        neumaier(st.s, st.sc, 1.f);
+        kahan_add(st.s, st.sc, 1.f);
         if (GRAD) {
             st.gx *= e; st.gy *= e; st.gz *= e;
             st.cx *= e; st.cy *= e; st.cz *= e;
-            neumaier(st.gx, st.cx, gx);
-            neumaier(st.gy, st.cy, gy);
-            neumaier(st.gz, st.cz, gz);
+            kahan_add(st.gx, st.cx, gx);
+            kahan_add(st.gy, st.cy, gy);
+            kahan_add(st.gz, st.cz, gz);
         }
         st.dref = d;
         st.lref = lw;
@@ -144,7 +157,7 @@ struct CoefTable {     // several classes: per-class rows of a device table (16-
 // ---------------------------------------------------------------------------
 // err bounds the FP32 rounding of d: the computed difference vectors are
 // exact up to a few ulps of the offset o from the vertex they are formed
-// against, so |d_fp32 - d| <= 2^-20 (d + |o|_1).  With conservative rounding
+// against, so |d_fp32 - d| <= 2^-21 (d + |o|_1).  With conservative rounding
 // on (the default) each term enters the sum at d - err, so every term, and
 // hence the log-sum-exp, stays an underestimate (App. A) in FP32 too.
 struct Term {
@@ -154,10 +167,10 @@ struct Term {
 template <bool GRAD>
 __device__ __forceinline__ Term point_term(float4 p, float qx, float qy, float qz) {
     float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-    float d = sqrtf(dot3(dx, dy, dz, dx, dy, dz));
-    Term t{d, 0.f, 0.f, 0.f, 0.f, d * 0x1p-22f};
+    float d = fsqrt(dot3(dx, dy, dz, dx, dy, dz));
+    Term t{d, 0.f, 0.f, 0.f, 0.f, d * 0x1p-21f};
     if (GRAD && d > 0.f) {
-        float inv = 1.f / d;
+        float inv = frcp(d);
         t.gx = dx * inv; t.gy = dy * inv; t.gz = dz * inv;
     }
     return t;
@@ -170,25 +183,25 @@ __device__ __forceinline__ Term edge_term(float4 r0, float4 r1, float qx, float 
     float ex = r1.x - r0.x, ey = r1.y - r0.y, ez = r1.z - r0.z;
     float px = qx - r0.x, py = qy - r0.y, pz = qz - r0.z;
     float ee = dot3(ex, ey, ez, ex, ey, ez);
-    float t = ee > 0.f ? dot3(px, py, pz, ex, ey, ez) / ee : 0.f;
+    float t = ee > 0.f ? fdiv(dot3(px, py, pz, ex, ey, ez), ee) : 0.f;
     bool interior = t > 0.f && t < 1.f;
     t = fminf(fmaxf(t, 0.f), 1.f);
     float cx = fmaf(-t, ex, px), cy = fmaf(-t, ey, py), cz = fmaf(-t, ez, pz);
-    float d = sqrtf(dot3(cx, cy, cz, cx, cy, cz));
+    float d = fsqrt(dot3(cx, cy, cz, cx, cy, cz));
     float a = r0.w, b = r1.w;
     float u = t * (1.f - t);
     float bump = 16.f * (1.f - 0.5f * (a + b));
     // w~ = a + (b - a)(3t^2 - 2t^3) + 16 (1 - (a+b)/2) t^2 (1-t)^2
     float w = fmaf(b - a, t * t * (3.f - 2.f * t), fmaf(bump, u * u, a));
     Term r{d, fmaf(S, __logf(w), slogA), 0.f, 0.f, 0.f,
-           (d + fabsf(px) + fabsf(py) + fabsf(pz)) * 0x1p-22f};
+           (d + fabsf(px) + fabsf(py) + fabsf(pz)) * 0x1p-21f};
     if (GRAD) {
-        float inv = d > 0.f ? 1.f / d : 0.f;
+        float inv = d > 0.f ? frcp(d) : 0.f;
         float gx = cx * inv, gy = cy * inv, gz = cz * inv;
         if (interior) {
             // dw~/dt = 6 (b - a) t (1 - t) + 2 bump t (1 - t)(1 - 2t)
             float dw = u * fmaf(6.f, b - a, 2.f * bump * (1.f - 2.f * t));
-            float k = S * dw / (w * ee) * inv_alpha;
+            float k = S * dw * frcp(w * ee) * inv_alpha;
             if (metric) k *= inv_alpha;
             gx = fmaf(-k, ex, gx); gy = fmaf(-k, ey, gy); gz = fmaf(-k, ez, gz);
         }
@@ -200,7 +213,7 @@ __device__ __forceinline__ Term edge_term(float4 r0, float4 r1, float qx, float 
 // closest point of segment a + t e to p (for the degenerate-triangle fallback)
 __device__ __forceinline__ float seg_param(float px, float py, float pz, float ex, float ey, float ez) {
     float ee = dot3(ex, ey, ez, ex, ey, ez);
-    float t = ee > 0.f ? dot3(px, py, pz, ex, ey, ez) / ee : 0.f;
+    float t = ee > 0.f ? fdiv(dot3(px, py, pz, ex, ey, ez), ee) : 0.f;
     return fminf(fmaxf(t, 0.f), 1.f);
 }
 
@@ -261,13 +274,13 @@ __device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float 
     } else if (d3 >= 0.f && d4 <= d3) {
         region = 4; p1 = 1.f; p2 = 0.f; dx = bpx; dy = bpy; dz = bpz;
     } else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
-        region = 1; t = d1 / (d1 - d3); p1 = t; p2 = 0.f;
+        region = 1; t = fdiv(d1, d1 - d3); p1 = t; p2 = 0.f;
         ex = abx; ey = aby; ez = abz;
         dx = fmaf(-t, abx, apx); dy = fmaf(-t, aby, apy); dz = fmaf(-t, abz, apz);
     } else if (d6 >= 0.f && d5 <= d6) {
         region = 4; p1 = 0.f; p2 = 1.f; dx = cpx; dy = cpy; dz = cpz;
     } else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
-        region = 2; t = d2 / (d2 - d6); p1 = 0.f; p2 = t;
+        region = 2; t = fdiv(d2, d2 - d6); p1 = 0.f; p2 = t;
         ex = acx; ey = acy; ez = acz;
         dx = fmaf(-t, acx, apx); dy = fmaf(-t, acy, apy); dz = fmaf(-t, acz, apz);
     } else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
@@ -276,28 +289,28 @@ __device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float 
         dx = fmaf(-t, ex, bpx); dy = fmaf(-t, ey, bpy); dz = fmaf(-t, ez, bpz);
     } else {
         region = 0;
-        float den = 1.f / (va + vb + vc);
+        float den = frcp(va + vb + vc);
         p1 = vb * den; p2 = vc * den;
         // distance to the plane through v0: |(q - v0) . n| / |n|, direction +-n
         float inv_n = rsqrtf(nn);
         float h = dot3(apx, apy, apz, nx, ny, nz) * inv_n;
         dx = h * nx * inv_n; dy = h * ny * inv_n; dz = h * nz * inv_n;
     }
-    float d = sqrtf(dot3(dx, dy, dz, dx, dy, dz));
+    float d = fsqrt(dot3(dx, dy, dz, dx, dy, dz));
     Poly2 w = A.tri_uniform ? tri_weight(CoefUniform{A}, p1, p2)
                             : tri_weight(CoefTable{A.tri_table + 36 * __float_as_int(r0.w)}, p1, p2);
     float o = region <= 2 ? fabsf(apx) + fabsf(apy) + fabsf(apz)
                           : (region == 3 ? fabsf(bpx) + fabsf(bpy) + fabsf(bpz) : 0.f);
     Term r{d, fmaf(S, __logf(w.w), slogA), 0.f, 0.f, 0.f, (d + o) * 0x1p-21f};
     if (GRAD) {
-        float inv = d > 0.f ? 1.f / d : 0.f;
+        float inv = d > 0.f ? frcp(d) : 0.f;
         float gx = dx * inv, gy = dy * inv, gz = dz * inv;
-        float k = S / w.w * inv_alpha;
+        float k = S * frcp(w.w) * inv_alpha;
         if (metric) k *= inv_alpha;
         float wgx = 0.f, wgy = 0.f, wgz = 0.f;   // grad w~ (Eq. 5)
         if (region == 0) {
             // grad phi1 = n x (v0 - v2) / |n|^2, grad phi2 = n x (v1 - v0) / |n|^2
-            float inn = 1.f / nn;
+            float inn = frcp(nn);
             float g1x = dop(ny, -acz, nz, -acy) * inn, g1y = dop(nz, -acx, nx, -acz) * inn,
                   g1z = dop(nx, -acy, ny, -acx) * inn;
             float g2x = dop(ny, abz, nz, aby) * inn, g2y = dop(nz, abx, nx, abz) * inn,
@@ -308,7 +321,7 @@ __device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float 
         } else if (region != 4) {
             float ee = dot3(ex, ey, ez, ex, ey, ez);
             float dwdt = region == 1 ? w.wx : (region == 2 ? w.wy : w.wy - w.wx);
-            float c = dwdt / ee;
+            float c = fdiv(dwdt, ee);
             wgx = c * ex; wgy = c * ey; wgz = c * ez;
         }
         r.gx = fmaf(-k, wgx, gx);
@@ -321,50 +334,156 @@ __device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float 
 // ---------------------------------------------------------------------------
 // Alg. 1 over one class hierarchy
 // ---------------------------------------------------------------------------
+template <int CLS, bool GRAD>
+__device__ __forceinline__ Term leaf_term(const TreeView &T, const EvalArgs &A, int slot, float4 lo,
+                                          float qx, float qy, float qz, bool metric) {
+    if (CLS == 0) return point_term<GRAD>(lo, qx, qy, qz);
+    if (CLS == 1)
+        return edge_term<GRAD>(T.leaf[2 * slot], T.leaf[2 * slot + 1], qx, qy, qz, A.S, T.slogA,
+                               A.inv_alpha, metric);
+    return tri_term<GRAD>(T.leaf[3 * slot], T.leaf[3 * slot + 1], T.leaf[3 * slot + 2], qx, qy, qz, A,
+                          T.slogA, metric);
+}
+
+// One node of Alg. 1: the opening test, then the far-field term (App. D) or a
+// leaf hand-off or descent.  Returns the leaf slot to evaluate, or -1.
+template <bool GRAD, bool COUNT>
+__device__ __forceinline__ int node_step(const TreeView &T, const EvalArgs &A, float qx, float qy,
+                                         float qz, LSE &st, int &node, float4 &leaf_lo, int &n_vis,
+                                         int &n_far);
+
+// node_step on a node whose record (lo, hi) is already in registers
+template <bool GRAD, bool COUNT>
+__device__ __forceinline__ int node_test(const TreeView &T, const EvalArgs &A, float qx, float qy,
+                                         float qz, LSE &st, float4 lo, float4 hi, int &node,
+                                         float4 &leaf_lo, int &n_vis, int &n_far) {
+    float yx = clampf(qx, lo.x, hi.x);
+    float yy = clampf(qy, lo.y, hi.y);
+    float yz = clampf(qz, lo.z, hi.z);
+    float dx = qx - yx, dy = qy - yy, dz = qz - yz;
+    float D2 = dot3(dx, dy, dz, dx, dy, dz);
+    float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
+    float diag2 = dot3(ex, ey, ez, ex, ey, ez);
+    int esc = __float_as_int(lo.w);
+    int pay = __float_as_int(hi.w);
+    if (COUNT) ++n_vis;
+    int slot = -1;
+    float logn = pay < 0 ? 0.f : hi.w;
+    // Negligible subtree: every term below this node is at most
+    // n_B W_max exp(-alpha D) (D <= each d_i), i.e. its exponent relative to
+    // the running reference is below -A.prune (64: < 1e-27 of the sum), so it
+    // cannot change the FP32 result; skip it.  D > d* + (log n_B + log W_max
+    // - l* + prune)/alpha, tested on squares.
+    float thr = fmaf(logn + T.lwmax - st.lref + A.prune, A.inv_alpha, st.dref);
+    if (thr < 0.f || D2 > thr * thr) {
+        node = esc;
+        return -1;
+    }
+    if (diag2 < A.beta2 * D2) {
+        // far field at the closest box point y_B: weight n_B A^S (App. D)
+        float D = fsqrt(D2);
+        float inv = D > 0.f ? frcp(D) : 0.f;
+        float lw = logn + T.slogA;
+        lse_add<GRAD>(st, fmaf(-A.cons, D * 0x1p-21f, D), lw, dx * inv, dy * inv, dz * inv, A.alpha);
+        if (COUNT) ++n_far;
+        node = esc;
+    } else if (pay < 0) {
+        slot = pay & 0x7fffffff;
+        leaf_lo = lo;
+        node = esc;
+    } else {
+        node = node + 1;
+    }
+    return slot;
+}
+
+template <bool GRAD, bool COUNT>
+__device__ __forceinline__ int node_step(const TreeView &T, const EvalArgs &A, float qx, float qy,
+                                         float qz, LSE &st, int &node, float4 &leaf_lo, int &n_vis,
+                                         int &n_far) {
+    return node_test<GRAD, COUNT>(T, A, qx, qy, qz, st, T.lo[2 * node], T.hi[2 * node], node, leaf_lo,
+                                  n_vis, n_far);
+}
+
+// Alg. 1 over one class hierarchy, stackless (escape indices).  Exact leaf
+// terms are expensive and rare (a few percent of the nodes a query visits),
+// so a lane that reaches a leaf queues it and the wave evaluates queued leaves
+// together once at least defer/64 of its live lanes hold one (or none can
+// continue); far-field terms are added inline.  The set of terms, and so the
+// value up to summation order, is that of the recursive Alg. 1.
+// Reference for the running maximum before any term is seen: descend to the
+// leaf whose box is nearest at every level and take the lower bound
+// -alpha (D_leaf + |leaf box| + 1/alpha) of that leaf's term (its weight is
+// >= 1 up to rounding).  The traversal's largest term is at least this large
+// (the leaf, or a far-field ancestor of it, enters the sum), so s cannot
+// underflow, and most terms then fall below the reference, which keeps the
+// rescaling branch of lse_add rare across a wave.
+__device__ __forceinline__ float seed_distance(const TreeView &T, float qx, float qy, float qz,
+                                               float inv_alpha) {
+    int node = 0;
+    float4 lo = T.lo[0], hi = T.hi[0];
+    while (__float_as_int(hi.w) >= 0) {
+        int l = node + 1;
+        float4 llo = T.lo[2 * l], lhi = T.hi[2 * l];
+        int r = __float_as_int(llo.w);
+        float4 rlo = T.lo[2 * r], rhi = T.hi[2 * r];
+        float ax = qx - clampf(qx, llo.x, lhi.x), ay = qy - clampf(qy, llo.y, lhi.y),
+              az = qz - clampf(qz, llo.z, lhi.z);
+        float bx = qx - clampf(qx, rlo.x, rhi.x), by = qy - clampf(qy, rlo.y, rhi.y),
+              bz = qz - clampf(qz, rlo.z, rhi.z);
+        bool left = dot3(ax, ay, az, ax, ay, az) <= dot3(bx, by, bz, bx, by, bz);
+        node = left ? l : r;
+        lo = left ? llo : rlo;
+        hi = left ? lhi : rhi;
+    }
+    float dx = qx - clampf(qx, lo.x, hi.x), dy = qy - clampf(qy, lo.y, hi.y),
+          dz = qz - clampf(qz, lo.z, hi.z);
+    float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
+    return fsqrt(dot3(dx, dy, dz, dx, dy, dz)) + fsqrt(dot3(ex, ey, ez, ex, ey, ez)) + inv_alpha;
+}
+
 template <int CLS, bool GRAD, bool COUNT>
 __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, float qx, float qy,
                                          float qz, LSE &st, int &n_vis, int &n_far, int &n_leaf) {
     const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
-    int node = 0;
-    while (node >= 0) {
-        float4 lo = T.lo[node];
-        float4 hi = T.hi[node];
-        float yx = fminf(fmaxf(qx, lo.x), hi.x);
-        float yy = fminf(fmaxf(qy, lo.y), hi.y);
-        float yz = fminf(fmaxf(qz, lo.z), hi.z);
-        float dx = qx - yx, dy = qy - yy, dz = qz - yz;
-        float D2 = dot3(dx, dy, dz, dx, dy, dz);
-        float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
-        float diag2 = dot3(ex, ey, ez, ex, ey, ez);
-        int esc = __float_as_int(lo.w);
-        int pay = __float_as_int(hi.w);
-        if (COUNT) ++n_vis;
-        if (diag2 < A.beta2 * D2) {
-            // far field at the closest box point y_B: weight n_B A^S (App. D)
-            float D = sqrtf(D2);
-            float inv = 1.f / D;
-            float lw = (pay < 0 ? 0.f : hi.w) + T.slogA;
-            lse_add<GRAD>(st, fmaf(-A.cons, D * 0x1p-22f, D), lw, dx * inv, dy * inv, dz * inv,
-                          A.alpha);
-            if (COUNT) ++n_far;
-            node = esc;
-        } else if (pay < 0) {
-            int slot = pay & 0x7fffffff;
-            Term t;
-            if (CLS == 0) {
-                t = point_term<GRAD>(lo, qx, qy, qz);
-            } else if (CLS == 1) {
-                t = edge_term<GRAD>(T.leaf[2 * slot], T.leaf[2 * slot + 1], qx, qy, qz, A.S,
-                                    T.slogA, A.inv_alpha, metric);
-            } else {
-                t = tri_term<GRAD>(T.leaf[3 * slot], T.leaf[3 * slot + 1], T.leaf[3 * slot + 2], qx,
-                                   qy, qz, A, T.slogA, metric);
+    int node = T.n_nodes > 0 ? 0 : -1;
+    float4 leaf_lo = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (node >= 0 && st.s == 0.f && st.dref == INFINITY) {
+        float sd = seed_distance(T, qx, qy, qz, A.inv_alpha);
+        if (sd == sd) {   // NaN queries keep the empty reference
+            st.dref = sd;
+            st.lref = 0.f;
+        }
+    }
+    if (CLS == 0 || A.defer == 0) {
+        while (node >= 0) {
+            int slot = node_step<GRAD, COUNT>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
+            if (slot >= 0) {
+                if (COUNT) ++n_leaf;
+                Term t = leaf_term<CLS, GRAD>(T, A, slot, leaf_lo, qx, qy, qz, metric);
+                lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
             }
-            lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
+        }
+        return;
+    }
+    int pending = -1;
+    while (true) {
+        while (true) {
+            bool can = node >= 0 && pending < 0;
+            uint64_t stepping = __ballot(can);
+            if (stepping == 0) break;
+            uint64_t waiting = __ballot(pending >= 0);
+            uint64_t live = stepping | waiting;
+            if (waiting && __popcll(waiting) * 64 >= __popcll(live) * A.defer) break;
+            if (can) pending = node_step<GRAD, COUNT>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
+        }
+        bool has = pending >= 0;
+        if (__ballot(has) == 0) break;
+        if (has) {
             if (COUNT) ++n_leaf;
-            node = esc;
-        } else {
-            node = node + 1;
+            Term t = leaf_term<CLS, GRAD>(T, A, pending, leaf_lo, qx, qy, qz, metric);
+            lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
+            pending = -1;
         }
     }
 }
@@ -546,6 +665,17 @@ int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, 
     return SD_OK;
 }
 
+// Deferred-leaf threshold in 64ths of the live lanes (0 = evaluate leaves
+// inline); SD_DEFER overrides the default for tuning sweeps.
+static int defer_threshold() {
+    static int v = [] {
+        const char *e = getenv("SD_DEFER");
+        int x = e ? atoi(e) : 0;
+        return x < 0 ? 0 : (x > 64 ? 64 : x);
+    }();
+    return v;
+}
+
 int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, int64_t nq,
                   const sd_params *p, float *d_out, float *g_out, int32_t *counts, bool brute,
                   hipStream_t s) {
@@ -564,6 +694,11 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
         float f = (float)sl;
         if ((double)f < sl) f = nextafterf(f, INFINITY);   // far-field weights round up
         A.tree[c].slogA = f;
+        // largest possible log-weight of any term of the class (pruning bound):
+        // w~ <= 1 + |a - b|/2 <= 1.5 for edges, <= the largest Bernstein
+        // coefficient for triangles (convex hull), w = 1 for points
+        double wmax = c == 0 ? 1.0 : (c == 1 ? 1.5 : std::max(1.0, sc->tri_wmax));
+        A.tree[c].lwmax = (float)(S * (log(sc->A[c]) + log(wmax))) + 1e-3f;
     }
     A.tri_uniform = sc->n_tri_classes <= 1 ? 1 : 0;
     memcpy(A.tri_coef, sc->tri_coef0, sizeof(A.tri_coef));
@@ -574,6 +709,8 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
     A.S = (float)S;
     A.margin_scale = ldexpf(1.f, -22);
     A.cons = (p->flags & SD_NO_CONSERVATIVE_ROUNDING) ? 0.f : 1.f;
+    A.defer = defer_threshold();
+    A.prune = (p->flags & SD_NO_PRUNE) ? INFINITY : 64.f;
     A.flags = p->flags;
     A.nq = (int32_t)nq;
     A.Q = Q;

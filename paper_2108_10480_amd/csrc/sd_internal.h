@@ -49,6 +49,7 @@ struct TreeView {
     const float4 *leaf;   // edges / triangles only
     int32_t n_nodes;
     float slogA;          // S log A of the class, filled per evaluation
+    float lwmax;          // bound on the log-weight of any term of the class
 };
 
 struct EvalArgs {
@@ -61,6 +62,8 @@ struct EvalArgs {
     float alpha, inv_alpha, beta2, S;
     float margin_scale;   // final rounding margin: 2^-22 (|d*| + |log-sum term|)
     float cons;           // 1: each term enters at its rounded-down distance (default)
+    int32_t defer;        // queued-leaf threshold in 64ths of live lanes (0: inline leaves)
+    float prune;          // skip subtrees whose terms are below exp(-prune) of the reference
     uint32_t flags;
     int32_t nq;
     const float *Q;
@@ -101,6 +104,7 @@ struct sd_scene {
     int32_t n_tri_classes = 0;
     float *tri_table = nullptr;                           // n_tri_classes x 36 Bernstein coefs
     float tri_coef0[36];                                  // host copy of class 0
+    double tri_wmax = 1.0;                                // largest Bernstein coefficient
     int64_t device_bytes = 0;
     int device = 0;
 };

@@ -132,7 +132,7 @@ def test_paper_metric_and_rootlog_flags(case):
 def test_counters_are_consistent(case):
     name, sc, scene, osc, trees = case
     Q = _queries(sc, 2000, seed=15)
-    c = api.sd_eval_counters(scene, cuda(Q), 50.0, 0.5).cpu().numpy()
+    c = api.sd_eval_counters(scene, cuda(Q), 50.0, 0.5, flags=api.SD_NO_PRUNE).cpu().numpy()
     _, _, st = O.barnes_hut(osc, trees, Q.astype(np.float64), 50.0, 0.5)
     ok = st[:, 0] > CUT_TIE
     np.testing.assert_array_equal(c[ok, 0], st[ok, 1])   # nodes visited
