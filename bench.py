@@ -23,6 +23,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue rate of the code as built (packed FP32 instructions are
+# disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 78.6
+ALU_PEAK_PACKED_TFLOPS = 157.3
+# algorithmic FLOPs per unit of work, value + gradient (see the design notes):
+F_QUERY = 50        # load, seed bookkeeping, finalisation
+F_NODE = 26         # box distance, box diagonal, opening and pruning tests
+F_FAR = 35          # sqrt, rcp, direction, exponent, compensated sums
+F_TRI_LEAF = 636    # distance + region, de Casteljau weight, gradient, sums
 METRIC = "smooth-distance+grad queries/s on 1 MI355X: BH vs surrogate at ≤1e-5 rel / 1e-3 abs"
 # algorithmic bytes per unit of work (see the design notes)
 B_QUERY = 12 + 16 + 4        # query in, value + gradient out, order index
@@ -154,6 +163,8 @@ def main():
     p99 = [float(x) for x in torch.quantile(cnt[:200000], 0.99, dim=0).cpu()]
     bytes_per_query = B_QUERY + B_NODE * nodes + B_TRI_LEAF * leaves
     achieved = n * bytes_per_query / (eval_ms * 1e-3) / 1e9
+    flops_per_query = F_QUERY + F_NODE * nodes + F_FAR * far + F_TRI_LEAF * leaves
+    tflops = n * flops_per_query / (eval_ms * 1e-3) / 1e12
     traffic = _traffic(os.path.join(ROOT, "paper_2108_10480_amd", "csrc", "eval.hip"))
 
     out = {
@@ -181,15 +192,19 @@ def main():
             "beta": args.beta,
         },
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "kernel": "k_eval (Barnes-Hut traversal, value+gradient)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "achieved": tflops,
+            "peak": ALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": tflops / ALU_PEAK_TFLOPS,
+            "frac_of_packed_peak": tflops / ALU_PEAK_PACKED_TFLOPS,
             "traffic": traffic,
-            "bytes_per_query": bytes_per_query,
+            "flops_per_query": flops_per_query,
             "kernel_ms": eval_ms,
+            "hbm_algorithmic": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": achieved / HBM_PEAK_GBS,
+                                "bytes_per_query": bytes_per_query},
         },
         "stages_ms": {"query_order": order_ms, "traversal": eval_ms, "build": min(builds)},
         "work_per_query": {"nodes": nodes, "far_terms": far, "leaves": leaves,

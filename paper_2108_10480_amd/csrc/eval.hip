@@ -442,9 +442,26 @@ __device__ __forceinline__ float seed_distance(const TreeView &T, float qx, floa
     return fsqrt(dot3(dx, dy, dz, dx, dy, dz)) + fsqrt(dot3(ex, ey, ez, ex, ey, ez)) + inv_alpha;
 }
 
+// Per-wave LDS queue of the cooperative leaf stage: queued leaf slots and their
+// results, lane-minor so that the 64 lanes touch consecutive banks.
+constexpr int kQ = 4;
+struct LeafQueue {
+    int slot[kQ][64];
+    int ent[kQ * 64];
+    float res[kQ][5][64];
+};
+
+// LDS written by some lanes of a wave and read by others: order within the wave
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int CLS, bool GRAD, bool COUNT>
 __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, float qx, float qy,
-                                         float qz, LSE &st, int &n_vis, int &n_far, int &n_leaf) {
+                                         float qz, LSE &st, int &n_vis, int &n_far, int &n_leaf,
+                                         LeafQueue &lq) {
     const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
     int node = T.n_nodes > 0 ? 0 : -1;
     float4 leaf_lo = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -466,25 +483,68 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
         }
         return;
     }
-    int pending = -1;
+    // Wave-cooperative leaves: a lane that reaches a leaf queues its slot (up to
+    // kQ per lane) in the wave's LDS queue and keeps traversing.  When a lane's
+    // queue is full, or no lane can continue, the wave evaluates every queued
+    // (query, leaf) pair with all lanes busy (the owner's query is read with a
+    // lane shuffle), then each owner folds its results into its own sum.
+    const int lane = __lane_id();
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int cnt = 0;
     while (true) {
         while (true) {
-            bool can = node >= 0 && pending < 0;
-            uint64_t stepping = __ballot(can);
-            if (stepping == 0) break;
-            uint64_t waiting = __ballot(pending >= 0);
-            uint64_t live = stepping | waiting;
-            if (waiting && __popcll(waiting) * 64 >= __popcll(live) * A.defer) break;
-            if (can) pending = node_step<GRAD, COUNT>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
+            bool can = node >= 0 && cnt < kQ;
+            if (__ballot(can) == 0) break;
+            if (__ballot(node >= 0 && cnt >= kQ)) break;   // flush before a lane stalls
+            if (can) {
+                int slot = node_step<GRAD, COUNT>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
+                if (slot >= 0) {
+                    lq.slot[cnt][lane] = slot;
+                    ++cnt;
+                    if (COUNT) ++n_leaf;
+                }
+            }
         }
-        bool has = pending >= 0;
-        if (__ballot(has) == 0) break;
-        if (has) {
-            if (COUNT) ++n_leaf;
-            Term t = leaf_term<CLS, GRAD>(T, A, pending, leaf_lo, qx, qy, qz, metric);
-            lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
-            pending = -1;
+        if (__ballot(cnt > 0) == 0) break;
+        // exclusive prefix of the per-lane counts (kQ <= 4: two bit planes)
+        int off = 0, total = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            uint64_t m = __ballot((cnt >> b) & 1);
+            total += __popcll(m) << b;
+            off += __popcll(m & lt) << b;
         }
+        for (int k = 0; k < cnt; ++k) lq.ent[off + k] = (lane << 2) | k;
+        wave_sync();
+        // spread the entries over the lanes still present in the wave (lanes
+        // past the end of the query array have already exited)
+        const uint64_t present = __ballot(true);
+        const int rank = __popcll(present & lt), npresent = __popcll(present);
+        for (int base = 0; base < total; base += npresent) {
+            int e = base + rank;
+            bool act = e < total;
+            int code = act ? lq.ent[e] : 0;
+            int owner = code >> 2, k = code & 3;
+            float ox = __shfl(qx, owner, 64), oy = __shfl(qy, owner, 64), oz = __shfl(qz, owner, 64);
+            if (act) {
+                Term t = leaf_term<CLS, GRAD>(T, A, lq.slot[k][owner], leaf_lo, ox, oy, oz, metric);
+                lq.res[k][0][owner] = fmaf(-A.cons, t.err, t.d);
+                lq.res[k][1][owner] = t.lw;
+                if (GRAD) {
+                    lq.res[k][2][owner] = t.gx;
+                    lq.res[k][3][owner] = t.gy;
+                    lq.res[k][4][owner] = t.gz;
+                }
+            }
+        }
+        wave_sync();
+        for (int k = 0; k < cnt; ++k) {
+            float gx = 0.f, gy = 0.f, gz = 0.f;
+            if (GRAD) { gx = lq.res[k][2][lane]; gy = lq.res[k][3][lane]; gz = lq.res[k][4][lane]; }
+            lse_add<GRAD>(st, lq.res[k][0][lane], lq.res[k][1][lane], gx, gy, gz, A.alpha);
+        }
+        cnt = 0;
+        wave_sync();
     }
 }
 
@@ -544,12 +604,14 @@ __global__ void __launch_bounds__(kB) k_eval(EvalArgs A) {
     int qi = A.perm ? (int)A.perm[i] : i;
     if ((unsigned)qi >= (unsigned)A.nq) return;
     float qx = A.Q[3 * (int64_t)qi], qy = A.Q[3 * (int64_t)qi + 1], qz = A.Q[3 * (int64_t)qi + 2];
+    __shared__ LeafQueue lqs[(MASK & 6) ? kB / 64 : 1];
+    LeafQueue &lq = lqs[(MASK & 6) ? threadIdx.x / 64 : 0];
     LSE st;
     lse_init(st);
     int nv = 0, nf = 0, nl = 0;
-    if (MASK & 1) traverse<0, GRAD, COUNT>(A.tree[0], A, qx, qy, qz, st, nv, nf, nl);
-    if (MASK & 2) traverse<1, GRAD, COUNT>(A.tree[1], A, qx, qy, qz, st, nv, nf, nl);
-    if (MASK & 4) traverse<2, GRAD, COUNT>(A.tree[2], A, qx, qy, qz, st, nv, nf, nl);
+    if (MASK & 1) traverse<0, GRAD, COUNT>(A.tree[0], A, qx, qy, qz, st, nv, nf, nl, lq);
+    if (MASK & 2) traverse<1, GRAD, COUNT>(A.tree[1], A, qx, qy, qz, st, nv, nf, nl, lq);
+    if (MASK & 4) traverse<2, GRAD, COUNT>(A.tree[2], A, qx, qy, qz, st, nv, nf, nl, lq);
     if (COUNT) {
         A.counts[3 * (int64_t)qi] = nv;
         A.counts[3 * (int64_t)qi + 1] = nf;
@@ -665,13 +727,12 @@ int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, 
     return SD_OK;
 }
 
-// Deferred-leaf threshold in 64ths of the live lanes (0 = evaluate leaves
-// inline); SD_DEFER overrides the default for tuning sweeps.
+// Leaf evaluation mode: 1 = wave-cooperative leaf stage (default), 0 = each
+// lane evaluates its leaves inline; SD_LEAF_MODE overrides it for comparisons.
 static int defer_threshold() {
     static int v = [] {
-        const char *e = getenv("SD_DEFER");
-        int x = e ? atoi(e) : 0;
-        return x < 0 ? 0 : (x > 64 ? 64 : x);
+        const char *e = getenv("SD_LEAF_MODE");
+        return e ? (atoi(e) != 0 ? 1 : 0) : 1;
     }();
     return v;
 }

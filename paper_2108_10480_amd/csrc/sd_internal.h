@@ -62,7 +62,7 @@ struct EvalArgs {
     float alpha, inv_alpha, beta2, S;
     float margin_scale;   // final rounding margin: 2^-22 (|d*| + |log-sum term|)
     float cons;           // 1: each term enters at its rounded-down distance (default)
-    int32_t defer;        // queued-leaf threshold in 64ths of live lanes (0: inline leaves)
+    int32_t defer;        // 1: wave-cooperative leaf stage, 0: leaves evaluated inline
     float prune;          // skip subtrees whose terms are below exp(-prune) of the reference
     uint32_t flags;
     int32_t nq;
