@@ -99,7 +99,7 @@ extern "C" int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64
                                 float *Xbar, void *stream) {
     if (m < 0 || K < 0) return sd::fail(SD_EINVAL, "sd_rigid_adjoint: negative size");
     if (K == 0) return SD_OK;
-    if (!X || !R || !gbar || !grad || !Rbar || !tbar)
+    if (!R || !Rbar || !tbar || (m > 0 && (!X || !gbar || !grad)))
         return sd::fail(SD_EINVAL, "sd_rigid_adjoint: null pointer");
     if (K > 0x7fffffff) return sd::fail(SD_EUNSUPPORTED, "sd_rigid_adjoint: too many transforms");
     hipStream_t s = (hipStream_t)stream;
