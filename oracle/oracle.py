@@ -13,7 +13,8 @@ What lives here (each function cites the passage it follows):
 * global weight scale A per class ............... Sec. 3.3, App. C.2, App. C.3
 * brute-force and Barnes-Hut evaluation ......... Eq. 3, Eq. 4, Alg. 1, Alg. 2
   (in C, see sd_oracle.c)
-* the surrogate network in FP64 (forward, backward, input gradient)
+* the surrogate network in FP64 (forward, backward, input gradient, Adam):
+  see ``mlp.py``
 
 Readings of ambiguous passages (each also listed in the design notes):
 * App. C.2's derivative constraints are read as w'(0) = w'(1) = 0.

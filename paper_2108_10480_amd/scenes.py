@@ -207,3 +207,56 @@ def scene_aabb(scene):
         used.append(V[scene.T.reshape(-1)])
     X = np.concatenate(used) if used else np.zeros((1, 3), np.float32)
     return X.min(0).astype(np.float64), X.max(0).astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# inputs of the learned surrogate: frequencies, initial weights, sample sets
+# --------------------------------------------------------------------------
+SURR_N_FREQ = 64
+SURR_WIDTH = 256
+SURR_DEPTH = 4
+
+
+def surrogate_param_shapes():
+    """Flat parameter order of the surrogate network: W1 (256x128), b1,
+    W2..W4 (256x256) with their biases, w5 (256), b5 (1); matrices are
+    out x in, row-major."""
+    shapes = [(SURR_WIDTH, 2 * SURR_N_FREQ), (SURR_WIDTH,)]
+    for _ in range(SURR_DEPTH - 1):
+        shapes += [(SURR_WIDTH, SURR_WIDTH), (SURR_WIDTH,)]
+    return shapes + [(SURR_WIDTH,), (1,)]
+
+
+def fourier_matrix(seed=11, sigma=2.0, n_freq=SURR_N_FREQ):
+    """Random Fourier frequencies B ~ N(0, sigma^2), n_freq x 3, float32."""
+    return _f32(np.random.default_rng(seed).normal(0.0, sigma, (n_freq, 3)))
+
+
+def surrogate_init(seed=12):
+    """Initial parameters, flat float32: every matrix and bias of a layer with
+    fan-in k drawn from U(-1/sqrt(k), 1/sqrt(k)); the output bias is 0."""
+    rng = np.random.default_rng(seed)
+    fan_in = [2 * SURR_N_FREQ] * 2 + [SURR_WIDTH] * (2 * (SURR_DEPTH - 1) + 1)
+    parts = []
+    for shp, k in zip(surrogate_param_shapes()[:-1], fan_in):
+        lim = 1.0 / np.sqrt(k)
+        parts.append(rng.uniform(-lim, lim, int(np.prod(shp))))
+    parts.append(np.zeros(1))
+    return _f32(np.concatenate(parts))
+
+
+def surrogate_samples(scene, n, seed=6, near_frac=0.7, offset=0.5, box=1.5):
+    """Training points: a fraction near_frac on area-weighted random triangle
+    points moved along the face normal by U[-offset, offset], the rest uniform
+    in [-box, box]^3."""
+    rng = np.random.default_rng(seed)
+    n_near = int(round(n * near_frac))
+    near = surface_samples(scene.V, scene.T, n_near, rng, -offset, offset)
+    far = rng.uniform(-box, box, (n - n_near, 3))
+    X = np.concatenate([near, far])
+    return _f32(X[rng.permutation(n)])
+
+
+def epoch_order(n, epoch, seed=13):
+    """Shuffled sample order of one training epoch, int32."""
+    return _i32(np.random.default_rng([seed, epoch]).permutation(n))
