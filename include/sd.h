@@ -191,6 +191,98 @@ int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64_t K,
                      const float *gbar, const float *grad,
                      float *Rbar, float *tbar, float *Xbar, void *stream);
 
+/*
+ * Learned surrogate of the smooth distance.  The paper has no learned part:
+ * this network approximates d of Eq. 3 for one scene and one (alpha, alpha_u,
+ * beta, flags) setting, is trained on values the exact evaluation produces,
+ * and hands queries near the zero isosurface back to the exact Barnes-Hut
+ * evaluation (Alg. 1, Alg. 2).
+ *
+ * Architecture (fixed):
+ *   gamma(x) = [sin(2 pi B x), cos(2 pi B x)]     B: 64 x 3 (row-major)
+ *   z_l = W_l a_{l-1} + b_l,  a_l = z_l / (1 + exp(-z_l)),  l = 1..4, width 256
+ *   y = w5 . a_4 + b5
+ * Parameters: SD_SURR_N_PARAMS FP32 values, in this order (matrices out x in,
+ * row-major): W1 (256 x 128), b1, W2 (256 x 256), b2, W3, b3, W4, b4, w5 (256),
+ * b5.  The FP32 values are the master copy trained by Adam; evaluation and
+ * training products use W1..W4 and w5 rounded to BF16 (nearest even) on the
+ * matrix cores with FP32 accumulation; biases stay FP32.
+ *
+ * A handle owns its device buffers (master weights, Adam moments, packed BF16
+ * weights, a training workspace for max_batch rows).  Calls on one handle
+ * must not overlap (training mutates it); sd_surrogate_forward and
+ * sd_eval_surrogate only read it.
+ */
+#define SD_SURR_N_FREQ 64
+#define SD_SURR_WIDTH 256
+#define SD_SURR_DEPTH 4
+#define SD_SURR_N_PARAMS 230657
+
+typedef struct sd_surrogate sd_surrogate;
+
+/* B_host: 64 x 3 frequencies; theta_host: initial parameters (both host, FP32,
+ * copied).  max_batch: largest training batch, a multiple of 64 (0 = inference
+ * only).  Adam moments start at zero, step 0, certified margin +inf.
+ * Synchronises `stream` once.  SD_ENOMEM when the workspace does not fit. */
+int sd_surrogate_create(const float *B_host, const float *theta_host, int64_t max_batch,
+                        void *stream, sd_surrogate **out);
+int sd_surrogate_free(sd_surrogate *sur);
+
+/* Surrogate value d_out (nQ) and, when grad_out is not NULL, its gradient in x
+ * (nQ x 3), for the queries Q (nQ x 3).  Asynchronous. */
+int sd_surrogate_forward(const sd_surrogate *sur, const float *Q, int64_t nQ, float *d_out,
+                         float *grad_out, void *stream);
+
+/* Mean squared error L = mean_b (y(x_b) - label_b)^2 over one batch and its
+ * gradient dL/dtheta (SD_SURR_N_PARAMS FP32, device) with the batch rows
+ * x_b = X[idx[b]], label_b = labels[idx[b]] (idx NULL: rows 0..n-1).  X holds
+ * n_rows x 3 values and labels n_rows; an index outside [0, n_rows) makes the
+ * loss and gradient NaN.  n is a positive multiple of 64, at most max_batch.
+ * grad_out / loss_out (device, may be NULL) receive copies.  Asynchronous. */
+int sd_surrogate_loss_grad(sd_surrogate *sur, const float *X, const float *labels, int64_t n_rows,
+                           const int32_t *idx, int64_t n, float *grad_out, float *loss_out,
+                           void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments) on
+ * the master weights with the gradient grad (device; NULL = the handle's last
+ * sd_surrogate_loss_grad result) and learning rate lr >= 0; then refreshes
+ * the BF16 copies.  Asynchronous. */
+int sd_surrogate_adam(sd_surrogate *sur, const float *grad, float lr, void *stream);
+
+/* sd_surrogate_loss_grad followed by sd_surrogate_adam.  Asynchronous. */
+int sd_surrogate_train_step(sd_surrogate *sur, const float *X, const float *labels, int64_t n_rows,
+                            const int32_t *idx, int64_t n, float lr, float *loss_out,
+                            void *stream);
+
+/* Certified margin: eps = safety * max_i |y(X_i) - labels_i| over a held-out
+ * set (n rows, device), stored in the handle and returned in *eps_host.
+ * safety >= 1.  Synchronises `stream`. */
+int sd_surrogate_certify(sd_surrogate *sur, const float *X, const float *labels, int64_t n,
+                         float safety, void *stream, float *eps_host);
+
+/* Host copies of the state (every output may be NULL): master parameters,
+ * Adam moments (SD_SURR_N_PARAMS each), frequencies (64 x 3), step count,
+ * certified margin.  Synchronous (device-wide). */
+int sd_surrogate_save(const sd_surrogate *sur, float *theta_host, float *m_host, float *v_host,
+                      float *B_host, int64_t *step_host, float *eps_host);
+
+/* Replace the master parameters (and the Adam moments, zero when NULL), step
+ * count and certified margin from host arrays. */
+int sd_surrogate_load(sd_surrogate *sur, const float *theta_host, const float *m_host,
+                      const float *v_host, int64_t step, float eps_cert, void *stream);
+
+/* Smooth distance and gradient with the surrogate where it is certified:
+ * every query gets the surrogate value y and gradient; the queries with
+ * |y| < band + eps_cert (the certified margin of sd_surrogate_certify) are
+ * then evaluated exactly (sd_eval_grad semantics with `params`, in Morton
+ * order unless SD_NO_QUERY_SORT) and overwritten.  routed (nQ bytes, may be
+ * NULL) receives 1 for those queries.  *n_fallback_host (may be NULL) receives
+ * their number.  The surrogate must have been trained for this scene and
+ * params.  Synchronises `stream` once (to size the exact pass). */
+int sd_eval_surrogate(const sd_scene *scene, const sd_surrogate *sur, const float *Q, int64_t nQ,
+                      const sd_params *params, float band, float *d_out, float *grad_out,
+                      uint8_t *routed, int64_t *n_fallback_host, void *stream);
+
 const char *sd_last_error(void);
 
 #ifdef __cplusplus

@@ -600,7 +600,7 @@ __device__ __forceinline__ void lse_init(LSE &st) {
 template <bool GRAD, bool COUNT, int MASK>
 __global__ void __launch_bounds__(kB) k_eval(EvalArgs A) {
     int i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
-    if (i >= A.nq) return;
+    if (i >= A.nthr) return;
     int qi = A.perm ? (int)A.perm[i] : i;
     if ((unsigned)qi >= (unsigned)A.nq) return;
     float qx = A.Q[3 * (int64_t)qi], qy = A.Q[3 * (int64_t)qi + 1], qz = A.Q[3 * (int64_t)qi + 2];
@@ -673,11 +673,13 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 }
 
 __global__ void __launch_bounds__(kB)
-k_query_keys(const float *__restrict__ Q, int64_t n, float lx, float ly, float lz, float sx,
-             float sy, float sz, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+k_query_keys(const float *__restrict__ Q, const uint32_t *__restrict__ idx, int64_t n, float lx,
+             float ly, float lz, float sx, float sy, float sz, uint64_t *__restrict__ keys,
+             uint32_t *__restrict__ vals) {
     int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (i >= n) return;
-    float u[3] = {(Q[3 * i] - lx) * sx, (Q[3 * i + 1] - ly) * sy, (Q[3 * i + 2] - lz) * sz};
+    int64_t j = idx ? (int64_t)idx[i] : i;
+    float u[3] = {(Q[3 * j] - lx) * sx, (Q[3 * j + 1] - ly) * sy, (Q[3 * j + 2] - lz) * sz};
     uint32_t c = 0;
     for (int a = 0; a < 3; ++a) {
         float v = fminf(fmaxf(u[a], 0.f), 1.f);   // NaN -> 0
@@ -685,7 +687,7 @@ k_query_keys(const float *__restrict__ Q, int64_t n, float lx, float ly, float l
         c |= spread10(q) << (2 - a);
     }
     keys[i] = c;
-    vals[i] = (uint32_t)i;
+    vals[i] = (uint32_t)j;
 }
 
 template <bool GRAD, bool COUNT>
@@ -702,8 +704,10 @@ void launch_eval(const EvalArgs &A, int mask, unsigned grid, hipStream_t s) {
 }  // namespace
 
 // Morton order of the queries in the scene box enlarged by half its extent on
-// every side (queries outside clamp to the boundary cells).
-int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s) {
+// every side (queries outside clamp to the boundary cells).  With idx, only the
+// n queries idx[0..n) are ordered and perm receives those indices sorted.
+int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s,
+                const uint32_t *idx) {
     if (nq <= 0) return SD_OK;
     uint64_t *keys, *keys2;
     uint32_t *vals2;
@@ -720,7 +724,7 @@ int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, 
         ext[a] = 2.f * e;
     }
     unsigned grid = (unsigned)((nq + kB - 1) / kB);
-    hipLaunchKernelGGL(k_query_keys, dim3(grid), dim3(kB), 0, s, Q, nq, lo[0], lo[1], lo[2],
+    hipLaunchKernelGGL(k_query_keys, dim3(grid), dim3(kB), 0, s, Q, idx, nq, lo[0], lo[1], lo[2],
                        1.f / ext[0], 1.f / ext[1], 1.f / ext[2], keys, perm);
     SD_TRY(radix_sort_pairs(keys, perm, keys2, vals2, nq, 30, temp, s));
     for (void *ptr : {(void *)keys, (void *)keys2, (void *)vals2, temp}) SD_HIP(hipFreeAsync(ptr, s));
@@ -739,9 +743,12 @@ static int defer_threshold() {
 
 int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, int64_t nq,
                   const sd_params *p, float *d_out, float *g_out, int32_t *counts, bool brute,
-                  hipStream_t s) {
-    if (nq == 0) return SD_OK;
+                  hipStream_t s, int64_t nthr) {
+    if (nthr < 0) nthr = nq;
+    if (nq == 0 || nthr == 0) return SD_OK;
     if (nq > (int64_t)0x7fffffff - kB) return fail(SD_EUNSUPPORTED, "more than 2^31 queries per call");
+    if (nthr != nq && (!perm_in || brute || counts || nthr > nq))
+        return fail(SD_EINVAL, "a thread count below the query count needs an index list");
     EvalArgs A;
     memset(&A, 0, sizeof(A));
     double alpha = p->alpha;
@@ -774,12 +781,13 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
     A.prune = (p->flags & SD_NO_PRUNE) ? INFINITY : 64.f;
     A.flags = p->flags;
     A.nq = (int32_t)nq;
+    A.nthr = (int32_t)nthr;
     A.Q = Q;
     A.d_out = d_out;
     A.g_out = g_out;
     A.counts = counts;
     int mask = (sc->n[0] > 0 ? 1 : 0) | (sc->n[1] > 0 ? 2 : 0) | (sc->n[2] > 0 ? 4 : 0);
-    unsigned grid = (unsigned)((nq + kB - 1) / kB);
+    unsigned grid = (unsigned)((nthr + kB - 1) / kB);
 
     if (mask == 0) {
         // empty scene: the empty sum gives +inf and a zero gradient

@@ -1,0 +1,1023 @@
+// Learned surrogate of the smooth distance (Eq. 3): a Fourier-feature SiLU
+// network, trained on values the exact method produces and evaluated on the
+// BF16 matrix cores with FP32 accumulation.  Queries whose surrogate value
+// lies in a band around the zero isosurface go back to the exact Barnes-Hut
+// evaluation (Alg. 1, Alg. 2).  The paper has no learned part; this file is
+// the library's extension of it.
+//
+// Network:  gamma(x) = [sin 2 pi B x, cos 2 pi B x]  (B: 64 x 3)
+//           z_l = W_l a_{l-1} + b_l,  a_l = silu(z_l)  (l = 1..4, width 256)
+//           y = w5 . a_4 + b5
+// Matrices W_l and w5 are used in BF16 (rounded to nearest even from the FP32
+// masters); biases stay FP32.
+//
+// Inference kernel (value and input gradient, reverse mode):
+//   One wave owns 32 queries (two 16-query blocks) and computes each layer as
+//   (out features x queries) += W (out x in) * A (in x queries) with
+//   v_mfma_f32_16x16x32_bf16: weight fragments are the A operand, activations
+//   the B operand.  A 16x16 accumulator tile holds, in lane l and register r,
+//   feature 4 (l / 16) + r of the tile for query l % 16.  The K index of the
+//   next layer is permuted so that tiles 2k and 2k+1 of one layer's output are,
+//   lane for lane, the B operand of K-block k of the next layer: the
+//   activations never leave the registers.  The weight fragments are packed
+//   in that permuted order once per weight update and streamed through LDS in
+//   16 KB chunks shared by the workgroup's four waves.  The derivative of
+//   silu at every hidden unit is kept in registers (BF16) for the backward
+//   sweep; the last layer's never needs storing.
+//   The network runs in a base-2 scaled domain: a'_l = log2(e) a_l, so that
+//   the logistic function is 1 / (1 + 2^-z') with z' the scaled
+//   pre-activation (one exp2 and one rcp per unit); scaling the first layer's
+//   input and the biases by log2(e) and w5 by 1/log2(e) leaves every weight
+//   matrix unchanged.
+//
+// Training kernels: plain tiled BF16 MFMA GEMMs over a batch (forward with a
+// fused bias + silu epilogue, backward input products with the fused silu'
+// product, weight gradients as split-K products reduced in a fixed order),
+// a loss kernel, column sums, and Adam on FP32 master weights.
+#include <math.h>
+#include <vector>
+
+#include "sd_internal.h"
+
+namespace sd {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NF = 64;          // Fourier frequencies
+constexpr int NIN = 2 * NF;     // first-layer inputs
+constexpr int WD = 256;         // hidden width
+constexpr int64_t NPAR = 230657;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kInvLog2e = 0.6931471805599453f;
+
+__host__ __device__ constexpr int64_t off_W(int l) {   // l = 1..4
+    return l == 1 ? 0 : (int64_t)WD * NIN + WD + (int64_t)(l - 2) * (WD * WD + WD);
+}
+__host__ __device__ constexpr int fan_in(int l) { return l == 1 ? NIN : WD; }
+__host__ __device__ constexpr int64_t off_b(int l) { return off_W(l) + (int64_t)WD * fan_in(l); }
+constexpr int64_t OFF_W5 = off_b(4) + WD;
+constexpr int64_t OFF_B5 = OFF_W5 + WD;
+static_assert(OFF_B5 + 1 == NPAR, "parameter layout");
+
+// inference weight stream: 56 chunks of 16 fragments x 64 lanes x 16 bytes
+constexpr int kChunkU4 = 16 * 64;
+constexpr int kChunksFwd = 4 + 3 * 8;        // W1 (4 K-blocks), W2..W4 (8 each)
+constexpr int kChunks = kChunksFwd + 3 * 8 + 4;  // then W4..W2 transposed, W1 transposed
+constexpr int kQW = 32;                       // queries per wave
+constexpr int kQB = 4 * kQW;                  // queries per workgroup
+
+__device__ __forceinline__ uint32_t pk2(float lo, float hi) {
+    f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ __bf16 to_bf(float f) { return (__bf16)f; }
+
+__device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// sin and cos of 2 pi t with the hardware sine (argument in revolutions)
+__device__ __forceinline__ void sincos_rev(float t, float &s, float &c) {
+    float r = t - rintf(t);
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+}
+
+// K index of the permuted order: K-block kb, lane group g = lane / 16, j = 0..7
+__host__ __device__ __forceinline__ int perm_k(int kb, int g, int j) {
+    return 32 * kb + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+}
+
+// ---------------------------------------------------------------------------
+// weight packing (after every update)
+// ---------------------------------------------------------------------------
+__global__ void k_pack_infer(const float *__restrict__ th, uint16_t *__restrict__ frag,
+                             float *__restrict__ bias_s, float *__restrict__ w5s) {
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n_el = (int64_t)kChunks * kChunkU4 * 8;
+    if (e < n_el) {
+        int c = (int)(e / (kChunkU4 * 8));
+        int rem = (int)(e % (kChunkU4 * 8));
+        int t = rem / 512, lane = (rem / 8) % 64, j = rem % 8;
+        int g = lane >> 4, li = lane & 15;
+        int64_t src;
+        if (c < 4) {                           // W1, forward: row = out, K = in
+            src = off_W(1) + (int64_t)(16 * t + li) * NIN + perm_k(c, g, j);
+        } else if (c < kChunksFwd) {           // W2..W4 forward
+            int l = 2 + (c - 4) / 8, kb = (c - 4) % 8;
+            src = off_W(l) + (int64_t)(16 * t + li) * WD + perm_k(kb, g, j);
+        } else if (c < kChunksFwd + 24) {      // W4..W2 backward: row = in, K = out
+            int l = 4 - (c - kChunksFwd) / 8, kb = (c - kChunksFwd) % 8;
+            src = off_W(l) + (int64_t)perm_k(kb, g, j) * WD + 16 * t + li;
+        } else {                               // W1 backward: two K-blocks per chunk
+            int kb = 2 * (c - kChunksFwd - 24) + (t >> 3), it = t & 7;
+            src = off_W(1) + (int64_t)perm_k(kb, g, j) * NIN + 16 * it + li;
+        }
+        frag[e] = __builtin_bit_cast(uint16_t, to_bf(th[src]));
+    }
+    if (e < 4 * WD) bias_s[e] = kLog2e * th[off_b(1 + (int)(e / WD)) + e % WD];
+    if (e < WD) w5s[e] = (float)to_bf(th[OFF_W5 + e]) * kInvLog2e;
+}
+
+// BF16 copies for training: rows (out x in) and transposes (in x out)
+__global__ void k_pack_train(const float *__restrict__ th, __bf16 *__restrict__ wr,
+                             __bf16 *__restrict__ wc) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= NPAR) return;
+    __bf16 b = to_bf(th[i]);
+    wr[i] = b;
+    for (int l = 1; l <= 4; ++l) {
+        int64_t o = off_W(l), n = (int64_t)WD * fan_in(l);
+        if (i >= o && i < o + n) {
+            int64_t r = (i - o) / fan_in(l), k = (i - o) % fan_in(l);
+            wc[o + k * WD + r] = b;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// inference: value (and input gradient), optional routing flag
+// ---------------------------------------------------------------------------
+struct MlpArgs {
+    const u32x4 *frag;
+    const float *bias_s;
+    const float *w5s;
+    const float *b5;       // device scalar
+    const float *Bf;       // 64 x 3
+    const float *Q;
+    int64_t nq;
+    float *d_out;
+    float *g_out;          // nullptr: value only
+    uint8_t *routed;       // nullptr: no routing flag
+    float band;            // routed[i] = |d_i| < band
+    const float *label;    // certification: |d_i - label_i| -> err_out
+    float *err_out;
+};
+
+struct Pipe {
+    u32x4 *lds;            // two 16 KB slots
+    const u32x4 *src;
+    int tid;
+    u32x4 pf[2][4];
+    template <int C> __device__ __forceinline__ void load() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pf[C & 1][k] = src[(int64_t)C * kChunkU4 + tid + 256 * k];
+    }
+    template <int C> __device__ __forceinline__ void store() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lds[(C & 1) * kChunkU4 + tid + 256 * k] = pf[C & 1][k];
+    }
+    // Chunk C is readable in LDS.  Before computing it: store chunk C+1
+    // (loaded two chunks ago), start loading chunk C+3.
+    template <int C, int LAST> __device__ __forceinline__ void pre() {
+        if constexpr (C + 1 <= LAST) store<C + 1>();
+        if constexpr (C + 3 <= LAST) load<C + 3>();
+    }
+    template <int C> __device__ __forceinline__ const u32x4 *slot() const {
+        return lds + (C & 1) * kChunkU4;
+    }
+};
+
+// one 16 KB chunk of a 256-wide layer: 16 output tiles, K-block KB
+template <int C, int LAST, int KB>
+__device__ __forceinline__ void chunk_full(Pipe &P, const u32x4 (&bop)[8][2], f32x4 (&acc)[16][2],
+                                           int lane) {
+    P.pre<C, LAST>();
+    const u32x4 *w = P.slot<C>();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        u32x4 a = w[t * 64 + lane];
+        acc[t][0] = mma(a, bop[KB][0], acc[t][0]);
+        acc[t][1] = mma(a, bop[KB][1], acc[t][1]);
+    }
+    __syncthreads();
+}
+
+template <int C0, int LAST, int NKB>
+__device__ __forceinline__ void layer_full(Pipe &P, const u32x4 (&bop)[8][2], f32x4 (&acc)[16][2],
+                                           int lane) {
+    chunk_full<C0, LAST, 0>(P, bop, acc, lane);
+    chunk_full<C0 + 1, LAST, 1>(P, bop, acc, lane);
+    chunk_full<C0 + 2, LAST, 2>(P, bop, acc, lane);
+    chunk_full<C0 + 3, LAST, 3>(P, bop, acc, lane);
+    if constexpr (NKB == 8) {
+        chunk_full<C0 + 4, LAST, 4>(P, bop, acc, lane);
+        chunk_full<C0 + 5, LAST, 5>(P, bop, acc, lane);
+        chunk_full<C0 + 6, LAST, 6>(P, bop, acc, lane);
+        chunk_full<C0 + 7, LAST, 7>(P, bop, acc, lane);
+    }
+}
+
+// first-layer backward chunk: K-blocks 2p, 2p+1 x 8 tiles of gamma features
+template <int C, int LAST, int PAIR>
+__device__ __forceinline__ void chunk_w1t(Pipe &P, const u32x4 (&bop)[8][2], f32x4 (&acc)[16][2],
+                                          int lane) {
+    P.pre<C, LAST>();
+    const u32x4 *w = P.slot<C>();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        u32x4 a = w[t * 64 + lane];
+        constexpr int kb0 = 2 * PAIR;
+        const int kb = kb0 + (t >> 3), it = t & 7;
+        acc[it][0] = mma(a, bop[kb][0], acc[it][0]);
+        acc[it][1] = mma(a, bop[kb][1], acc[it][1]);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void init_bias(f32x4 (&acc)[16][2], const float *b, int g) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        f32x4 v = *(const f32x4 *)(b + 16 * t + 4 * g);
+        acc[t][0] = v;
+        acc[t][1] = v;
+    }
+}
+
+__device__ __forceinline__ void zero_acc(f32x4 (&acc)[16][2]) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[t][0] = acc[t][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+}
+
+// scaled silu: s = 1 / (1 + 2^-z'), a' = z' s, silu'(z) = s + a' (1 - s) / log2(e)
+__device__ __forceinline__ void silu_s(float z, float &a, float &d) {
+    float s = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-z));
+    a = z * s;
+    d = fmaf(a, fmaf(-s, kInvLog2e, kInvLog2e), s);
+}
+
+// hidden-layer epilogue: next B operand from a', stored silu' (BF16 pairs)
+template <bool KEEP>
+__device__ __forceinline__ void epi_hidden(const f32x4 (&acc)[16][2], u32x4 (&bop)[8][2],
+                                           uint32_t (&S)[16][2][2]) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+            float a[4], d[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) silu_s(acc[t][qb][r], a[r], d[r]);
+            bop[t >> 1][qb][(t & 1) * 2] = pk2(a[0], a[1]);
+            bop[t >> 1][qb][(t & 1) * 2 + 1] = pk2(a[2], a[3]);
+            if (KEEP) {
+                S[t][qb][0] = pk2(d[0], d[1]);
+                S[t][qb][1] = pk2(d[2], d[3]);
+            }
+        }
+}
+
+// backward epilogue: u = g * silu'(z) of the layer below, as the next B operand
+__device__ __forceinline__ void epi_back(const f32x4 (&acc)[16][2], u32x4 (&bop)[8][2],
+                                         const uint32_t (&S)[16][2][2]) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+            const f32x4 g = acc[t][qb];
+            float u0 = g[0] * bf_lo(S[t][qb][0]), u1 = g[1] * bf_hi(S[t][qb][0]);
+            float u2 = g[2] * bf_lo(S[t][qb][1]), u3 = g[3] * bf_hi(S[t][qb][1]);
+            bop[t >> 1][qb][(t & 1) * 2] = pk2(u0, u1);
+            bop[t >> 1][qb][(t & 1) * 2 + 1] = pk2(u2, u3);
+        }
+}
+
+template <bool GRAD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_mlp(MlpArgs A) {
+    __shared__ u32x4 lds[2 * kChunkU4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, li = lane & 15;
+    constexpr int LAST = GRAD ? kChunks - 1 : kChunksFwd - 1;
+
+    Pipe P;
+    P.lds = lds;
+    P.src = A.frag;
+    P.tid = tid;
+    P.load<0>();
+    P.store<0>();
+    P.load<1>();
+    P.load<2>();
+
+    const int64_t q0 = (int64_t)blockIdx.x * kQB + wave * kQW + li;
+    float x[2][3];
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb) {
+        int64_t q = q0 + 16 * qb;
+        bool live = q < A.nq;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[qb][a] = live ? A.Q[3 * q + a] : 0.f;
+    }
+
+    // first-layer input: lane holds gamma features 16 t + 4 g + r, t = 0..7
+    // (sines for t < 4, cosines of the same frequencies for t >= 4)
+    u32x4 bop[8][2];
+    {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float s[2][4], c[2][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float *b = A.Bf + 3 * (16 * t + 4 * g + r);
+                float b0 = b[0], b1 = b[1], b2 = b[2];
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb) {
+                    float th = fmaf(b0, x[qb][0], fmaf(b1, x[qb][1], b2 * x[qb][2]));
+                    sincos_rev(th, s[qb][r], c[qb][r]);
+                }
+            }
+#pragma unroll
+            for (int qb = 0; qb < 2; ++qb) {
+                // tile t -> K-block t / 2, half t % 2; tile t + 4 -> K-block 2 + t / 2
+                bop[t >> 1][qb][(t & 1) * 2] = pk2(kLog2e * s[qb][0], kLog2e * s[qb][1]);
+                bop[t >> 1][qb][(t & 1) * 2 + 1] = pk2(kLog2e * s[qb][2], kLog2e * s[qb][3]);
+                bop[2 + (t >> 1)][qb][(t & 1) * 2] = pk2(kLog2e * c[qb][0], kLog2e * c[qb][1]);
+                bop[2 + (t >> 1)][qb][(t & 1) * 2 + 1] = pk2(kLog2e * c[qb][2], kLog2e * c[qb][3]);
+            }
+        }
+    }
+    __syncthreads();
+
+    f32x4 acc[16][2];
+    uint32_t S1[16][2][2], S2[16][2][2], S3[16][2][2];
+
+    init_bias(acc, A.bias_s, g);
+    layer_full<0, LAST, 4>(P, bop, acc, lane);
+    epi_hidden<GRAD>(acc, bop, S1);
+    init_bias(acc, A.bias_s + WD, g);
+    layer_full<4, LAST, 8>(P, bop, acc, lane);
+    epi_hidden<GRAD>(acc, bop, S2);
+    init_bias(acc, A.bias_s + 2 * WD, g);
+    layer_full<12, LAST, 8>(P, bop, acc, lane);
+    epi_hidden<GRAD>(acc, bop, S3);
+    init_bias(acc, A.bias_s + 3 * WD, g);
+    layer_full<20, LAST, 8>(P, bop, acc, lane);
+
+    // output layer and the seed of the backward sweep: u4 = (w5 / log2 e) silu'(z4)
+    float y[2] = {0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        f32x4 w = *(const f32x4 *)(A.w5s + 16 * t + 4 * g);
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+            float a[4], d[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                silu_s(acc[t][qb][r], a[r], d[r]);
+                y[qb] = fmaf(a[r], w[r], y[qb]);
+            }
+            if (GRAD) {
+                bop[t >> 1][qb][(t & 1) * 2] = pk2(w[0] * d[0], w[1] * d[1]);
+                bop[t >> 1][qb][(t & 1) * 2 + 1] = pk2(w[2] * d[2], w[3] * d[3]);
+            }
+        }
+    }
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb) {
+        y[qb] += __shfl_xor(y[qb], 16);
+        y[qb] += __shfl_xor(y[qb], 32);
+        y[qb] += *A.b5;
+    }
+
+    float gx[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    if constexpr (GRAD) {
+        zero_acc(acc);
+        layer_full<28, LAST, 8>(P, bop, acc, lane);   // through W4
+        epi_back(acc, bop, S3);
+        zero_acc(acc);
+        layer_full<36, LAST, 8>(P, bop, acc, lane);   // through W3
+        epi_back(acc, bop, S2);
+        zero_acc(acc);
+        layer_full<44, LAST, 8>(P, bop, acc, lane);   // through W2
+        epi_back(acc, bop, S1);
+        zero_acc(acc);
+        chunk_w1t<52, LAST, 0>(P, bop, acc, lane);    // through W1
+        chunk_w1t<53, LAST, 1>(P, bop, acc, lane);
+        chunk_w1t<54, LAST, 2>(P, bop, acc, lane);
+        chunk_w1t<55, LAST, 3>(P, bop, acc, lane);
+        // acc[it] holds dy/d(a'_0) for gamma features 16 it + 4 g + r;
+        // dy/dgamma = log2(e) acc; chain through sin and cos of 2 pi b.x
+        const float cg = kLog2e * 6.283185307179586f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float *b = A.Bf + 3 * (16 * t + 4 * g + r);
+                float b0 = b[0], b1 = b[1], b2 = b[2];
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb) {
+                    float s, c;
+                    float th = fmaf(b0, x[qb][0], fmaf(b1, x[qb][1], b2 * x[qb][2]));
+                    sincos_rev(th, s, c);
+                    float k = cg * (acc[t][qb][r] * c - acc[t + 4][qb][r] * s);
+                    gx[qb][0] = fmaf(k, b0, gx[qb][0]);
+                    gx[qb][1] = fmaf(k, b1, gx[qb][1]);
+                    gx[qb][2] = fmaf(k, b2, gx[qb][2]);
+                }
+            }
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gx[qb][a] += __shfl_xor(gx[qb][a], 16);
+                gx[qb][a] += __shfl_xor(gx[qb][a], 32);
+            }
+    }
+
+    if (g == 0) {
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+            int64_t q = q0 + 16 * qb;
+            if (q >= A.nq) continue;
+            if (A.d_out) A.d_out[q] = y[qb];
+            if (GRAD && A.g_out) {
+                A.g_out[3 * q] = gx[qb][0];
+                A.g_out[3 * q + 1] = gx[qb][1];
+                A.g_out[3 * q + 2] = gx[qb][2];
+            }
+            if (A.routed) A.routed[q] = fabsf(y[qb]) < A.band ? 1 : 0;
+            if (A.err_out) A.err_out[q] = fabsf(y[qb] - A.label[q]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// training
+// ---------------------------------------------------------------------------
+// gamma(x) of the batch rows (x = X[idx[b]]), rows and transposed copies; a
+// row index outside [0, n_rows) reads as NaN (the loss becomes NaN)
+__global__ void k_fourier_rows(const float *__restrict__ X, int64_t n_rows,
+                               const int32_t *__restrict__ idx, int64_t n, const float *__restrict__ Bf,
+                               __bf16 *__restrict__ A0, __bf16 *__restrict__ A0T) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n * NF) return;
+    int64_t b = i / NF;
+    int m = (int)(i % NF);
+    int64_t src = idx ? (int64_t)idx[b] : b;
+    float th = NAN;
+    if (src >= 0 && src < n_rows)
+        th = fmaf(Bf[3 * m], X[3 * src], fmaf(Bf[3 * m + 1], X[3 * src + 1], Bf[3 * m + 2] * X[3 * src + 2]));
+    float s, c;
+    sincos_rev(th, s, c);
+    A0[b * NIN + m] = to_bf(s);
+    A0[b * NIN + NF + m] = to_bf(c);
+    A0T[(int64_t)m * n + b] = to_bf(s);
+    A0T[(int64_t)(NF + m) * n + b] = to_bf(c);
+}
+
+enum { EPI_FWD = 0, EPI_BWD = 1, EPI_PART = 2 };
+
+struct GemmArgs {
+    const __bf16 *A;     // M x K, row-major
+    int64_t lda;
+    const __bf16 *Bt;    // N x K, row-major (the right operand transposed)
+    int64_t ldb;
+    int M, N, K, kchunk;
+    const float *bias;   // EPI_FWD: N
+    const float *S_in;   // EPI_BWD: M x N multiplier
+    float *S_out;        // EPI_FWD: silu'(z), M x N
+    float *F_out;        // EPI_FWD: silu(z) in FP32, M x N (optional)
+    __bf16 *O_row;       // M x N
+    __bf16 *O_col;       // N x M (ld = M)
+    float *P_out;        // EPI_PART: gridDim.z x M x N
+};
+
+// C (M x N) = A (M x K) B (K x N): 64 x 64 tile per workgroup, 32 x 32 per wave
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs G) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, li = lane & 15;
+    const int m0 = blockIdx.y * 64 + (wave & 1) * 32, n0 = blockIdx.x * 64 + (wave >> 1) * 32;
+    const int kbeg = blockIdx.z * G.kchunk, kend = min(G.K, kbeg + G.kchunk);
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) acc[i][0] = acc[i][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const __bf16 *pa0 = G.A + (int64_t)(m0 + li) * G.lda + 8 * g;
+    const __bf16 *pa1 = pa0 + 16 * G.lda;
+    const __bf16 *pb0 = G.Bt + (int64_t)(n0 + li) * G.ldb + 8 * g;
+    const __bf16 *pb1 = pb0 + 16 * G.ldb;
+#pragma unroll 2
+    for (int k = kbeg; k < kend; k += 32) {
+        u32x4 a0 = *(const u32x4 *)(pa0 + k), a1 = *(const u32x4 *)(pa1 + k);
+        u32x4 b0 = *(const u32x4 *)(pb0 + k), b1 = *(const u32x4 *)(pb1 + k);
+        acc[0][0] = mma(a0, b0, acc[0][0]);
+        acc[0][1] = mma(a0, b1, acc[0][1]);
+        acc[1][0] = mma(a1, b0, acc[1][0]);
+        acc[1][1] = mma(a1, b1, acc[1][1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + 16 * j + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + 16 * i + 4 * g + r;
+                const int64_t o = (int64_t)m * G.N + n;
+                float v = acc[i][j][r];
+                if (EPI == EPI_FWD) {
+                    float z = v + G.bias[n];
+                    float s = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-z * kLog2e));
+                    float a = z * s;
+                    G.S_out[o] = s * fmaf(z, 1.f - s, 1.f);
+                    if (G.F_out) G.F_out[o] = a;
+                    G.O_row[o] = to_bf(a);
+                    G.O_col[(int64_t)n * G.M + m] = to_bf(a);
+                } else if (EPI == EPI_BWD) {
+                    float u = v * G.S_in[o];
+                    G.O_row[o] = to_bf(u);
+                    G.O_col[(int64_t)n * G.M + m] = to_bf(u);
+                } else {
+                    G.P_out[(int64_t)blockIdx.z * G.M * G.N + o] = v;
+                }
+            }
+        }
+}
+
+// output layer and loss: y_b = w5 . a4_b + b5, r_b = y_b - t_b, dy_b = 2 r_b / n,
+// G4 = dy_b w5 silu'(z4_b) (rows and transposed), dyr_b = (dy_b, r_b^2).
+// One wave per sample.
+__global__ void __launch_bounds__(256)
+k_out_loss(const float *__restrict__ A4, const float *__restrict__ S4, const __bf16 *__restrict__ w5,
+           const float *__restrict__ b5, const float *__restrict__ t, int64_t n_rows,
+           const int32_t *__restrict__ idx, int64_t n, float inv_n, __bf16 *__restrict__ G4, __bf16 *__restrict__ G4T, float *__restrict__ dyr) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= n) return;
+    float w[4], s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        w[k] = (float)w5[4 * lane + k];
+        s = fmaf(A4[b * WD + 4 * lane + k], w[k], s);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    float y = s + *b5;
+    const int64_t src = idx ? (int64_t)idx[b] : b;
+    float r = y - (src >= 0 && src < n_rows ? t[src] : NAN);
+    float dy = 2.f * r * inv_n;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int f = 4 * lane + k;
+        __bf16 u = to_bf(dy * w[k] * S4[b * WD + f]);
+        G4[b * WD + f] = u;
+        G4T[(int64_t)f * n + b] = u;
+    }
+    if (lane == 0) {
+        dyr[2 * b] = dy;
+        dyr[2 * b + 1] = r * r;
+    }
+}
+
+// partial column sums: part[chunk][c] = sum over rows of the chunk of
+// scale[row] * src[row][c] (fixed order)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_colsum(const T *__restrict__ src, int cols, int64_t rows, int64_t rows_per_chunk,
+         const float *__restrict__ scale, int scale_ld, float *__restrict__ part) {
+    const int c = threadIdx.x;
+    if (c >= cols) return;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+    const int64_t r1 = min(rows, r0 + rows_per_chunk);
+    float s = 0.f;
+    for (int64_t r = r0; r < r1; ++r) {
+        float v = (float)src[r * cols + c];
+        s = scale ? fmaf(scale[r * scale_ld], v, s) : s + v;
+    }
+    part[(int64_t)blockIdx.x * cols + c] = s;
+}
+
+// out[i] = scale * sum over chunks of part[chunk * ld + i], in chunk order
+__global__ void k_reduce_chunks(const float *__restrict__ part, int chunks, int64_t len, int64_t ld,
+                                float *__restrict__ out, float scale) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * ld + i];
+    out[i] = s * scale;
+}
+
+// b1, b2 and their complements c1 = 1 - b1, c2 = 1 - b2 are each the FP32
+// rounding of the exact constant (1 - b formed in FP32 would be off by the
+// rounding of b, 1.3e-5 relative for 0.999)
+__global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ gr, int64_t n, float lr, float b1, float b2,
+                       float c1, float c2, float eps, float inv_bc1, float inv_bc2) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float g = gr[i];
+    float mi = fmaf(b1, m[i], c1 * g);
+    float vi = fmaf(b2, v[i], c2 * g * g);
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi * inv_bc1) / (sqrtf(vi * inv_bc2) + eps);
+}
+
+// largest value of a non-negative array (NaN counts as +inf)
+__global__ void __launch_bounds__(256) k_max_part(const float *__restrict__ x, int64_t n,
+                                                  float *__restrict__ part) {
+    __shared__ float red[256];
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        float v = x[i];
+        m = (v != v) ? INFINITY : fmaxf(m, v);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_flags_u32(const uint8_t *__restrict__ f, int64_t n, uint32_t *__restrict__ o) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) o[i] = f[i];
+}
+
+__global__ void k_compact(const uint8_t *__restrict__ f, const uint32_t *__restrict__ pos, int64_t n,
+                          uint32_t *__restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n && f[i]) idx[pos[i]] = (uint32_t)i;
+}
+
+unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+}  // namespace sd
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct sd_surrogate {
+    int device = 0;
+    int64_t max_batch = 0;
+    int64_t step = 0;
+    float eps_cert = INFINITY;
+    float *Bf = nullptr;           // 64 x 3
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    uint16_t *frag = nullptr;      // inference stream
+    float *bias_s = nullptr, *w5s = nullptr;
+    __bf16 *wr = nullptr, *wc = nullptr;   // training copies
+    // training workspace (max_batch rows)
+    __bf16 *A0 = nullptr, *A0T = nullptr, *Ar[4] = {}, *AT[4] = {}, *Gr[4] = {}, *GT[4] = {};
+    float *S[4] = {}, *A4f = nullptr, *dyr = nullptr, *part = nullptr, *loss = nullptr;
+    int64_t part_len = 0;
+    std::vector<void *> owned;
+};
+
+namespace sd {
+namespace {
+
+constexpr int kSplitRows = 2048;   // split-K length of the weight-gradient products
+
+int sur_alloc(sd_surrogate *h, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(SD_ENOMEM, "surrogate: device allocation of " + std::to_string(bytes) +
+                                   " bytes failed");
+    }
+    h->owned.push_back(*p);
+    return SD_OK;
+}
+
+int pack(sd_surrogate *h, hipStream_t s) {
+    const int64_t n_el = (int64_t)kChunks * kChunkU4 * 8;
+    hipLaunchKernelGGL(k_pack_infer, dim3(blocks(n_el)), dim3(256), 0, s, h->theta, h->frag,
+                       h->bias_s, h->w5s);
+    hipLaunchKernelGGL(k_pack_train, dim3(blocks(NPAR)), dim3(256), 0, s, h->theta, h->wr, h->wc);
+    SD_HIP(hipGetLastError());
+    return SD_OK;
+}
+
+int launch_mlp(const sd_surrogate *h, const float *Q, int64_t nq, float *d, float *gr,
+               uint8_t *routed, float band, const float *label, float *err, hipStream_t s) {
+    if (nq <= 0) return SD_OK;
+    MlpArgs A;
+    A.frag = (const u32x4 *)h->frag;
+    A.bias_s = h->bias_s;
+    A.w5s = h->w5s;
+    A.b5 = h->theta + OFF_B5;
+    A.Bf = h->Bf;
+    A.Q = Q;
+    A.nq = nq;
+    A.d_out = d;
+    A.g_out = gr;
+    A.routed = routed;
+    A.band = band;
+    A.label = label;
+    A.err_out = err;
+    unsigned grid = (unsigned)((nq + kQB - 1) / kQB);
+    if (gr) hipLaunchKernelGGL(k_mlp<true>, dim3(grid), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL(k_mlp<false>, dim3(grid), dim3(256), 0, s, A);
+    SD_HIP(hipGetLastError());
+    return SD_OK;
+}
+
+int gemm(int epi, const GemmArgs &G, int splits, hipStream_t s) {
+    dim3 grid(G.N / 64, G.M / 64, splits);
+    if (epi == EPI_FWD) hipLaunchKernelGGL(k_gemm<EPI_FWD>, grid, dim3(256), 0, s, G);
+    else if (epi == EPI_BWD) hipLaunchKernelGGL(k_gemm<EPI_BWD>, grid, dim3(256), 0, s, G);
+    else hipLaunchKernelGGL(k_gemm<EPI_PART>, grid, dim3(256), 0, s, G);
+    SD_HIP(hipGetLastError());
+    return SD_OK;
+}
+
+// loss gradient of one batch into h->grad and the loss into h->loss
+int loss_grad(sd_surrogate *h, const float *X, const float *y, int64_t n_rows, const int32_t *idx,
+              int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fourier_rows, dim3(blocks(n * NF)), dim3(256), 0, s, X, n_rows, idx, n, h->Bf,
+                       h->A0, h->A0T);
+    // forward
+    for (int l = 1; l <= 4; ++l) {
+        GemmArgs G = {};
+        G.A = l == 1 ? h->A0 : h->Ar[l - 2];
+        G.lda = fan_in(l);
+        G.Bt = h->wr + off_W(l);
+        G.ldb = fan_in(l);
+        G.M = (int)n; G.N = WD; G.K = fan_in(l); G.kchunk = fan_in(l);
+        G.bias = h->theta + off_b(l);
+        G.S_out = h->S[l - 1];
+        G.F_out = l == 4 ? h->A4f : nullptr;
+        G.O_row = h->Ar[l - 1];
+        G.O_col = h->AT[l - 1];
+        SD_TRY(gemm(EPI_FWD, G, 1, s));
+    }
+    hipLaunchKernelGGL(k_out_loss, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, h->A4f, h->S[3],
+                       h->wr + OFF_W5, h->theta + OFF_B5, y, n_rows, idx, n, 1.f / (float)n, h->Gr[3], h->GT[3], h->dyr);
+    // backward through W4..W2 (dL/dz of the layer below)
+    for (int l = 4; l >= 2; --l) {
+        GemmArgs G = {};
+        G.A = h->Gr[l - 1];
+        G.lda = WD;
+        G.Bt = h->wc + off_W(l);
+        G.ldb = WD;
+        G.M = (int)n; G.N = WD; G.K = WD; G.kchunk = WD;
+        G.S_in = h->S[l - 2];
+        G.O_row = h->Gr[l - 2];
+        G.O_col = h->GT[l - 2];
+        SD_TRY(gemm(EPI_BWD, G, 1, s));
+    }
+    // weight gradients dW_l = G_l^T A_{l-1}, split over the batch
+    const int splits = (int)((n + kSplitRows - 1) / kSplitRows);
+    for (int l = 1; l <= 4; ++l) {
+        GemmArgs G = {};
+        G.A = h->GT[l - 1];
+        G.lda = n;
+        G.Bt = l == 1 ? h->A0T : h->AT[l - 2];
+        G.ldb = n;
+        G.M = WD; G.N = fan_in(l); G.K = (int)n; G.kchunk = kSplitRows;
+        G.P_out = h->part;
+        SD_TRY(gemm(EPI_PART, G, splits, s));
+        int64_t len = (int64_t)WD * fan_in(l);
+        hipLaunchKernelGGL(k_reduce_chunks, dim3(blocks(len)), dim3(256), 0, s, h->part, splits, len,
+                           len, h->grad + off_W(l), 1.f);
+        // bias: column sums of G_l
+        int64_t chunks = (n + kSplitRows - 1) / kSplitRows;
+        hipLaunchKernelGGL(k_colsum<__bf16>, dim3((unsigned)chunks), dim3(256), 0, s, h->Gr[l - 1], WD, n,
+                           (int64_t)kSplitRows, (const float *)nullptr, 0, h->part);
+        hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, s, h->part, (int)chunks, (int64_t)WD,
+                           (int64_t)WD, h->grad + off_b(l), 1.f);
+    }
+    // output layer: dw5 = sum dy a4, db5 = sum dy; loss = mean r^2
+    int64_t chunks = (n + kSplitRows - 1) / kSplitRows;
+    hipLaunchKernelGGL(k_colsum<float>, dim3((unsigned)chunks), dim3(256), 0, s, h->A4f, WD, n,
+                       (int64_t)kSplitRows, h->dyr, 2, h->part);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, s, h->part, (int)chunks, (int64_t)WD,
+                       (int64_t)WD, h->grad + OFF_W5, 1.f);
+    hipLaunchKernelGGL(k_colsum<float>, dim3((unsigned)chunks), dim3(256), 0, s, h->dyr, 2, n,
+                       (int64_t)kSplitRows, (const float *)nullptr, 0, h->part);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, s, h->part, (int)chunks, (int64_t)1,
+                       (int64_t)2, h->grad + OFF_B5, 1.f);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, s, h->part + 1, (int)chunks, (int64_t)1,
+                       (int64_t)2, h->loss, 1.f / (float)n);
+    SD_HIP(hipGetLastError());
+    return SD_OK;
+}
+
+}  // namespace
+}  // namespace sd
+
+using namespace sd;
+
+extern "C" int sd_surrogate_create(const float *B_host, const float *theta_host, int64_t max_batch,
+                                   void *stream, sd_surrogate **out) {
+    if (!out) return fail(SD_EINVAL, "sd_surrogate_create: null output");
+    *out = nullptr;
+    if (!B_host || !theta_host) return fail(SD_EINVAL, "sd_surrogate_create: null input");
+    if (max_batch < 0 || max_batch % 64 != 0 || max_batch > (1 << 24))
+        return fail(SD_EINVAL, "sd_surrogate_create: max_batch must be a multiple of 64 in [0, 2^24]");
+    hipStream_t s = (hipStream_t)stream;
+    auto *h = new sd_surrogate();
+    SD_HIP(hipGetDevice(&h->device));
+    h->max_batch = max_batch;
+    auto fl = [&](float **p, size_t n) { return sur_alloc(h, (void **)p, n * sizeof(float)); };
+    auto bf = [&](__bf16 **p, size_t n) { return sur_alloc(h, (void **)p, n * sizeof(__bf16)); };
+    int rc = SD_OK;
+    const int64_t n_el = (int64_t)kChunks * kChunkU4 * 8;
+    if (!rc) rc = fl(&h->Bf, 3 * NF);
+    if (!rc) rc = fl(&h->theta, NPAR);
+    if (!rc) rc = fl(&h->m, NPAR);
+    if (!rc) rc = fl(&h->v, NPAR);
+    if (!rc) rc = fl(&h->grad, NPAR);
+    if (!rc) rc = sur_alloc(h, (void **)&h->frag, n_el * sizeof(uint16_t));
+    if (!rc) rc = fl(&h->bias_s, 4 * WD);
+    if (!rc) rc = fl(&h->w5s, WD);
+    if (!rc) rc = bf(&h->wr, NPAR);
+    if (!rc) rc = bf(&h->wc, NPAR);
+    if (!rc) rc = fl(&h->loss, 1);
+    if (max_batch > 0) {
+        const size_t nb = (size_t)max_batch;
+        if (!rc) rc = bf(&h->A0, nb * NIN);
+        if (!rc) rc = bf(&h->A0T, nb * NIN);
+        for (int l = 0; l < 4 && !rc; ++l) {
+            rc = bf(&h->Ar[l], nb * WD);
+            if (!rc) rc = bf(&h->AT[l], nb * WD);
+            if (!rc) rc = bf(&h->Gr[l], nb * WD);
+            if (!rc) rc = bf(&h->GT[l], nb * WD);
+            if (!rc) rc = fl(&h->S[l], nb * WD);
+        }
+        if (!rc) rc = fl(&h->A4f, nb * WD);
+        if (!rc) rc = fl(&h->dyr, 2 * nb);
+        const int64_t splits = (max_batch + kSplitRows - 1) / kSplitRows;
+        h->part_len = splits * (int64_t)WD * WD;
+        if (!rc) rc = fl(&h->part, (size_t)h->part_len);
+    }
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(h->Bf, B_host, 3 * NF * sizeof(float), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->theta, theta_host, NPAR * sizeof(float), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(h->m, 0, NPAR * sizeof(float), s);
+        if (e == hipSuccess) e = hipMemsetAsync(h->v, 0, NPAR * sizeof(float), s);
+        if (e != hipSuccess) rc = fail(SD_EHIP, std::string("sd_surrogate_create: ") + hipGetErrorString(e));
+    }
+    if (!rc) rc = pack(h, s);
+    if (rc) {
+        for (void *p : h->owned) (void)hipFree(p);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return SD_OK;
+}
+
+extern "C" int sd_surrogate_free(sd_surrogate *h) {
+    if (!h) return SD_OK;
+    for (void *p : h->owned) (void)hipFree(p);
+    delete h;
+    return SD_OK;
+}
+
+extern "C" int sd_surrogate_forward(const sd_surrogate *h, const float *Q, int64_t nQ, float *d_out,
+                                    float *grad_out, void *stream) {
+    if (!h) return fail(SD_EINVAL, "sd_surrogate_forward: null handle");
+    if (nQ < 0) return fail(SD_EINVAL, "sd_surrogate_forward: nQ < 0");
+    if (nQ > 0 && (!Q || !d_out)) return fail(SD_EINVAL, "sd_surrogate_forward: null array");
+    return launch_mlp(h, Q, nQ, d_out, grad_out, nullptr, 0.f, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int sd_surrogate_loss_grad(sd_surrogate *h, const float *X, const float *y,
+                                      int64_t n_rows, const int32_t *idx, int64_t n, float *grad_out,
+                                      float *loss_out, void *stream) {
+    if (!h) return fail(SD_EINVAL, "sd_surrogate_loss_grad: null handle");
+    if (n <= 0 || n % 64 != 0 || n > h->max_batch)
+        return fail(SD_EINVAL, "sd_surrogate_loss_grad: batch must be a positive multiple of 64 "
+                               "no larger than max_batch");
+    if (!X || !y) return fail(SD_EINVAL, "sd_surrogate_loss_grad: null array");
+    if (!idx && n_rows < n) return fail(SD_EINVAL, "sd_surrogate_loss_grad: fewer rows than the batch");
+    hipStream_t s = (hipStream_t)stream;
+    SD_TRY(loss_grad(h, X, y, n_rows, idx, n, s));
+    if (grad_out) SD_HIP(hipMemcpyAsync(grad_out, h->grad, NPAR * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (loss_out) SD_HIP(hipMemcpyAsync(loss_out, h->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
+    return SD_OK;
+}
+
+extern "C" int sd_surrogate_adam(sd_surrogate *h, const float *grad, float lr, void *stream) {
+    if (!h) return fail(SD_EINVAL, "sd_surrogate_adam: null handle");
+    if (!(lr >= 0.f)) return fail(SD_EINVAL, "sd_surrogate_adam: lr must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const double b1 = 0.9, b2 = 0.999;
+    h->step += 1;
+    float ib1 = (float)(1.0 / (1.0 - pow(b1, (double)h->step)));
+    float ib2 = (float)(1.0 / (1.0 - pow(b2, (double)h->step)));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(NPAR)), dim3(256), 0, s, h->theta, h->m, h->v,
+                       grad ? grad : h->grad, NPAR, lr, (float)b1, (float)b2, (float)(1.0 - b1),
+                       (float)(1.0 - b2), 1e-8f, ib1, ib2);
+    SD_HIP(hipGetLastError());
+    return pack(h, s);
+}
+
+extern "C" int sd_surrogate_train_step(sd_surrogate *h, const float *X, const float *y,
+                                       int64_t n_rows, const int32_t *idx, int64_t n, float lr,
+                                       float *loss_out, void *stream) {
+    SD_TRY(sd_surrogate_loss_grad(h, X, y, n_rows, idx, n, nullptr, loss_out, stream));
+    return sd_surrogate_adam(h, nullptr, lr, stream);
+}
+
+extern "C" int sd_surrogate_certify(sd_surrogate *h, const float *X, const float *y, int64_t n,
+                                    float safety, void *stream, float *eps_host) {
+    if (!h) return fail(SD_EINVAL, "sd_surrogate_certify: null handle");
+    if (n <= 0 || !X || !y) return fail(SD_EINVAL, "sd_surrogate_certify: empty validation set");
+    if (!(safety >= 1.f)) return fail(SD_EINVAL, "sd_surrogate_certify: safety factor must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    float *err = nullptr, *part = nullptr;
+    const int nblk = 1024;
+    SD_HIP(hipMallocAsync((void **)&err, n * sizeof(float), s));
+    SD_HIP(hipMallocAsync((void **)&part, nblk * sizeof(float), s));
+    SD_TRY(launch_mlp(h, X, n, nullptr, nullptr, nullptr, 0.f, y, err, s));
+    hipLaunchKernelGGL(k_max_part, dim3(nblk), dim3(256), 0, s, err, n, part);
+    hipLaunchKernelGGL(k_max_part, dim3(1), dim3(256), 0, s, part, (int64_t)nblk, part);
+    SD_HIP(hipGetLastError());
+    float mx = 0.f;
+    SD_HIP(hipMemcpyAsync(&mx, part, sizeof(float), hipMemcpyDeviceToHost, s));
+    SD_HIP(hipFreeAsync(err, s));
+    SD_HIP(hipFreeAsync(part, s));
+    SD_HIP(hipStreamSynchronize(s));
+    h->eps_cert = safety * mx;
+    if (eps_host) *eps_host = h->eps_cert;
+    return SD_OK;
+}
+
+extern "C" int sd_surrogate_save(const sd_surrogate *h, float *theta_host, float *m_host, float *v_host,
+                                 float *B_host, int64_t *step_host, float *eps_host) {
+    if (!h) return fail(SD_EINVAL, "sd_surrogate_save: null handle");
+    if (theta_host) SD_HIP(hipMemcpy(theta_host, h->theta, NPAR * sizeof(float), hipMemcpyDeviceToHost));
+    if (m_host) SD_HIP(hipMemcpy(m_host, h->m, NPAR * sizeof(float), hipMemcpyDeviceToHost));
+    if (v_host) SD_HIP(hipMemcpy(v_host, h->v, NPAR * sizeof(float), hipMemcpyDeviceToHost));
+    if (B_host) SD_HIP(hipMemcpy(B_host, h->Bf, 3 * NF * sizeof(float), hipMemcpyDeviceToHost));
+    if (step_host) *step_host = h->step;
+    if (eps_host) *eps_host = h->eps_cert;
+    return SD_OK;
+}
+
+extern "C" int sd_surrogate_load(sd_surrogate *h, const float *theta_host, const float *m_host,
+                                 const float *v_host, int64_t step, float eps_cert, void *stream) {
+    if (!h || !theta_host) return fail(SD_EINVAL, "sd_surrogate_load: null argument");
+    if (step < 0) return fail(SD_EINVAL, "sd_surrogate_load: step < 0");
+    hipStream_t s = (hipStream_t)stream;
+    SD_HIP(hipMemcpyAsync(h->theta, theta_host, NPAR * sizeof(float), hipMemcpyHostToDevice, s));
+    if (m_host) SD_HIP(hipMemcpyAsync(h->m, m_host, NPAR * sizeof(float), hipMemcpyHostToDevice, s));
+    else SD_HIP(hipMemsetAsync(h->m, 0, NPAR * sizeof(float), s));
+    if (v_host) SD_HIP(hipMemcpyAsync(h->v, v_host, NPAR * sizeof(float), hipMemcpyHostToDevice, s));
+    else SD_HIP(hipMemsetAsync(h->v, 0, NPAR * sizeof(float), s));
+    h->step = step;
+    h->eps_cert = eps_cert;
+    return pack(h, s);
+}
+
+extern "C" int sd_eval_surrogate(const sd_scene *sc, const sd_surrogate *h, const float *Q, int64_t nQ,
+                                 const sd_params *p, float band, float *d_out, float *grad_out,
+                                 uint8_t *routed, int64_t *n_fallback_host, void *stream) {
+    if (!sc || !h || !p) return fail(SD_EINVAL, "sd_eval_surrogate: null argument");
+    if (nQ < 0) return fail(SD_EINVAL, "sd_eval_surrogate: nQ < 0");
+    if (!(band >= 0.f)) return fail(SD_EINVAL, "sd_eval_surrogate: band must be >= 0");
+    if (!(p->alpha > 0.f) || !(p->beta >= 0.f) || !(p->alpha_u >= 0.f))
+        return fail(SD_EINVAL, "sd_eval_surrogate: bad parameters");
+    if (sc->n[0] + sc->n[1] + sc->n[2] == 0) return fail(SD_EINVAL, "sd_eval_surrogate: empty scene");
+    if (nQ > 0x7fffffffll - 256) return fail(SD_EUNSUPPORTED, "sd_eval_surrogate: more than 2^31 queries");
+    if (n_fallback_host) *n_fallback_host = 0;
+    if (nQ == 0) return SD_OK;
+    if (!Q || !d_out || !grad_out) return fail(SD_EINVAL, "sd_eval_surrogate: null array");
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *flag = routed;
+    uint32_t *f32 = nullptr, *pos = nullptr, *idx = nullptr, *ord = nullptr;
+    void *temp = nullptr;
+    if (!flag) SD_HIP(hipMallocAsync((void **)&flag, nQ, s));
+    SD_TRY(launch_mlp(h, Q, nQ, d_out, grad_out, flag, band + h->eps_cert, nullptr, nullptr, s));
+    // compaction of the routed queries (in index order), then Morton order
+    SD_HIP(hipMallocAsync((void **)&f32, nQ * sizeof(uint32_t), s));
+    SD_HIP(hipMallocAsync((void **)&pos, nQ * sizeof(uint32_t), s));
+    SD_HIP(hipMallocAsync(&temp, radix_sort_temp_bytes(nQ), s));
+    hipLaunchKernelGGL(k_flags_u32, dim3(blocks(nQ)), dim3(256), 0, s, flag, nQ, f32);
+    SD_TRY(exclusive_scan_u32(f32, pos, nQ, temp, s));
+    uint32_t last_pos = 0;
+    uint8_t last_flag = 0;
+    SD_HIP(hipMemcpyAsync(&last_pos, pos + nQ - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SD_HIP(hipMemcpyAsync(&last_flag, flag + nQ - 1, 1, hipMemcpyDeviceToHost, s));
+    SD_HIP(hipStreamSynchronize(s));
+    const int64_t nfb = (int64_t)last_pos + last_flag;
+    int rc = SD_OK;
+    if (nfb > 0) {
+        SD_HIP(hipMallocAsync((void **)&idx, nfb * sizeof(uint32_t), s));
+        hipLaunchKernelGGL(k_compact, dim3(blocks(nQ)), dim3(256), 0, s, flag, pos, nQ, idx);
+        SD_HIP(hipGetLastError());
+        const uint32_t *perm = idx;
+        if (!(p->flags & SD_NO_QUERY_SORT) && nfb >= 4096) {
+            SD_HIP(hipMallocAsync((void **)&ord, nfb * sizeof(uint32_t), s));
+            rc = query_order(sc, Q, nfb, ord, s, idx);
+            perm = ord;
+        }
+        if (!rc) rc = eval_dispatch(sc, Q, perm, nQ, p, d_out, grad_out, nullptr, false, s, nfb);
+    }
+    for (void *ptr : {(void *)f32, (void *)pos, (void *)idx, (void *)ord, temp})
+        if (ptr) SD_HIP(hipFreeAsync(ptr, s));
+    if (!routed) SD_HIP(hipFreeAsync(flag, s));
+    if (n_fallback_host) *n_fallback_host = nfb;
+    return rc;
+}

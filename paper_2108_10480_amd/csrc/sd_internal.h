@@ -65,7 +65,8 @@ struct EvalArgs {
     int32_t defer;        // 1: wave-cooperative leaf stage, 0: leaves evaluated inline
     float prune;          // skip subtrees whose terms are below exp(-prune) of the reference
     uint32_t flags;
-    int32_t nq;
+    int32_t nq;            // number of queries (bound of the entries of perm)
+    int32_t nthr;          // number of threads: perm entries (nq without perm)
     const float *Q;
     const uint32_t *perm;  // optional query order (nullptr = identity)
     float *d_out;
@@ -111,8 +112,12 @@ struct sd_scene {
 
 namespace sd {
 // Query Morton ordering used by the evaluation (eval.hip)
-int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s);
+// With idx, only the queries idx[0..nq) are ordered (perm gets those indices).
+int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s,
+                const uint32_t *idx = nullptr);
+// nthr >= 0 with perm_in: nthr threads evaluate the queries perm_in[0..nthr)
+// out of nq; results land at the original query indices.
 int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, int64_t nq,
                   const sd_params *p, float *d_out, float *g_out, int32_t *counts, bool brute,
-                  hipStream_t s);
+                  hipStream_t s, int64_t nthr = -1);
 }  // namespace sd

@@ -35,12 +35,17 @@ def test_library_exports_every_declared_symbol(libsd):
 
 
 def test_python_binding_names_match_header():
-    from paper_2108_10480_amd import api
+    from paper_2108_10480_amd import api, surrogate
     declared = set(_declared())
     for n in declared:
         if n in ("sd_last_error", "sd_free_scene", "sd_scene_info_get"):
             continue
-        assert hasattr(api, n) or n.startswith("sd_surrogate"), n
+        if n.startswith("sd_surrogate_"):
+            meth = {"create": "__init__"}.get(n[len("sd_surrogate_"):], n[len("sd_surrogate_"):])
+            assert hasattr(surrogate.Surrogate, meth), n
+        else:
+            assert hasattr(api, n) or hasattr(surrogate, n), n
+        assert n in api.EXPORTED, n
 
 
 def test_triangle_weight_basis_matches_oracle(libsd, oracle_mod):

@@ -175,3 +175,25 @@ def test_bf16_rounding():
     x = np.random.default_rng(7).normal(0, 3, 100000).astype(np.float32)
     ref = torch.tensor(x).to(torch.bfloat16).to(torch.float32).numpy()
     assert np.array_equal(M.bf16_round(x), ref)
+
+
+def test_rounding_envelope_helper_reproduces_oracle():
+    """The tolerance helper of the surrogate parity tests, unperturbed, is the
+    oracle (so its rounding model cannot drift from the oracle's math)."""
+    from tests import surrogate_ref as R
+    th, B = _params(seed=8)
+    X = np.random.default_rng(9).uniform(-1.5, 1.5, (64, 3))
+    y, g = R.infer(th, B, X)
+    y0, g0 = M.input_grad(th, B, X)
+    np.testing.assert_allclose(y, y0, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(g, g0, rtol=1e-12, atol=1e-13)
+    t = np.random.default_rng(10).normal(0, 0.3, 64)
+    l, gr = R.loss_grad(th, B, X, t)
+    l0, gr0 = M.loss_grad(th, B, X, t)
+    assert abs(l - l0) < 1e-13
+    np.testing.assert_allclose(gr, gr0, rtol=1e-12, atol=1e-15)
+    # effective weights: BF16 matrices, FP32 biases
+    te = R.effective_theta(th.astype(np.float32))
+    p, q = M.unpack(te), M.unpack(th.astype(np.float32).astype(np.float64))
+    assert np.array_equal(p["b2"], q["b2"]) and not np.array_equal(p["W2"], q["W2"])
+    assert np.array_equal(p["W3"], M.bf16_round(q["W3"].astype(np.float32)).astype(np.float64))
