@@ -35,6 +35,9 @@
 // product, weight gradients as split-K products reduced in a fixed order),
 // a loss kernel, column sums, and Adam on FP32 master weights.
 #include <math.h>
+
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "sd_internal.h"
@@ -64,12 +67,11 @@ constexpr int64_t OFF_W5 = off_b(4) + WD;
 constexpr int64_t OFF_B5 = OFF_W5 + WD;
 static_assert(OFF_B5 + 1 == NPAR, "parameter layout");
 
-// inference weight stream: 56 chunks of 16 fragments x 64 lanes x 16 bytes
-constexpr int kChunkU4 = 16 * 64;
-constexpr int kChunksFwd = 4 + 3 * 8;        // W1 (4 K-blocks), W2..W4 (8 each)
-constexpr int kChunks = kChunksFwd + 3 * 8 + 4;  // then W4..W2 transposed, W1 transposed
-constexpr int kQW = 32;                       // queries per wave
-constexpr int kQB = 4 * kQW;                  // queries per workgroup
+// inference weight stream: 28 chunks of 32 fragments x 64 lanes x 16 bytes
+// (32 KB): four output tiles of 8 K-blocks, or eight of 4 for the first layer
+constexpr int kChunkU4 = 32 * 64;
+constexpr int kChunksFwd = 2 + 3 * 4;        // W1, W2..W4
+constexpr int kChunks = kChunksFwd + 3 * 4 + 2;  // then W4..W2 transposed, W1 transposed
 
 __device__ __forceinline__ uint32_t pk2(float lo, float hi) {
     f32x2 v = {lo, hi};
@@ -106,20 +108,21 @@ __global__ void k_pack_infer(const float *__restrict__ th, uint16_t *__restrict_
     if (e < n_el) {
         int c = (int)(e / (kChunkU4 * 8));
         int rem = (int)(e % (kChunkU4 * 8));
-        int t = rem / 512, lane = (rem / 8) % 64, j = rem % 8;
+        int f = rem / 512, lane = (rem / 8) % 64, j = rem % 8;
         int g = lane >> 4, li = lane & 15;
         int64_t src;
-        if (c < 4) {                           // W1, forward: row = out, K = in
-            src = off_W(1) + (int64_t)(16 * t + li) * NIN + perm_k(c, g, j);
-        } else if (c < kChunksFwd) {           // W2..W4 forward
-            int l = 2 + (c - 4) / 8, kb = (c - 4) % 8;
+        if (c < 2) {                           // W1 forward: 8 tiles x 4 K-blocks per chunk
+            int t = 8 * c + f / 4, kb = f % 4;
+            src = off_W(1) + (int64_t)(16 * t + li) * NIN + perm_k(kb, g, j);
+        } else if (c < kChunksFwd) {           // W2..W4 forward: 4 tiles x 8 K-blocks
+            int l = 2 + (c - 2) / 4, t = 4 * ((c - 2) % 4) + f / 8, kb = f % 8;
             src = off_W(l) + (int64_t)(16 * t + li) * WD + perm_k(kb, g, j);
-        } else if (c < kChunksFwd + 24) {      // W4..W2 backward: row = in, K = out
-            int l = 4 - (c - kChunksFwd) / 8, kb = (c - kChunksFwd) % 8;
+        } else if (c < kChunksFwd + 12) {      // W4..W2 transposed: tiles of inputs, K = outputs
+            int l = 4 - (c - kChunksFwd) / 4, t = 4 * ((c - kChunksFwd) % 4) + f / 8, kb = f % 8;
             src = off_W(l) + (int64_t)perm_k(kb, g, j) * WD + 16 * t + li;
-        } else {                               // W1 backward: two K-blocks per chunk
-            int kb = 2 * (c - kChunksFwd - 24) + (t >> 3), it = t & 7;
-            src = off_W(1) + (int64_t)perm_k(kb, g, j) * NIN + 16 * it + li;
+        } else {                               // W1 transposed: 8 tiles of gamma features
+            int t = 4 * (c - kChunksFwd - 12) + f / 8, kb = f % 8;
+            src = off_W(1) + (int64_t)perm_k(kb, g, j) * NIN + 16 * t + li;
         }
         frag[e] = __builtin_bit_cast(uint16_t, to_bf(th[src]));
     }
@@ -162,89 +165,90 @@ struct MlpArgs {
     float *err_out;
 };
 
+// Weight stream through LDS: three 32 KB slots.  Chunk k is loaded straight
+// into slot k % 3 (global_load_lds, lane i -> slot base + 16 i) at the start
+// of chunk k - 2; the barrier that ends chunk k - 1 waits for those loads.  So
+// while chunk k is being computed, chunk k + 1 is readable as well (the next
+// tile's fragments can be read ahead across a chunk boundary) and slot
+// (k + 2) % 3, last read during chunk k - 1, is being refilled.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(3))) char lds_char_t;
+constexpr int kSlots = 3;
+
+template <int NW>
 struct Pipe {
-    u32x4 *lds;            // two 16 KB slots
+    u32x4 *lds;
     const u32x4 *src;
-    int tid;
-    u32x4 pf[2][4];
+    int wave, lane;
     template <int C> __device__ __forceinline__ void load() {
+        constexpr int per_wave = kChunkU4 / NW;
+        const u32x4 *g = src + (int64_t)C * kChunkU4 + wave * per_wave + lane;
+        lds_char_t *l = (lds_char_t *)(lds + (C % kSlots) * kChunkU4 + wave * per_wave);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) pf[C & 1][k] = src[(int64_t)C * kChunkU4 + tid + 256 * k];
+        for (int k = 0; k < per_wave / 64; ++k)
+            __builtin_amdgcn_global_load_lds((const void *)(g + 64 * k), (lds_void_t *)(l + 1024 * k), 16, 0, 0);
     }
-    template <int C> __device__ __forceinline__ void store() {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) lds[(C & 1) * kChunkU4 + tid + 256 * k] = pf[C & 1][k];
-    }
-    // Chunk C is readable in LDS.  Before computing it: store chunk C+1
-    // (loaded two chunks ago), start loading chunk C+3.
     template <int C, int LAST> __device__ __forceinline__ void pre() {
-        if constexpr (C + 1 <= LAST) store<C + 1>();
-        if constexpr (C + 3 <= LAST) load<C + 3>();
+        if constexpr (C + 2 <= LAST) load<C + 2>();
     }
     template <int C> __device__ __forceinline__ const u32x4 *slot() const {
-        return lds + (C & 1) * kChunkU4;
+        return lds + (C % kSlots) * kChunkU4;
     }
 };
 
-// one 16 KB chunk of a 256-wide layer: 16 output tiles, K-block KB
-template <int C, int LAST, int KB>
-__device__ __forceinline__ void chunk_full(Pipe &P, const u32x4 (&bop)[8][2], f32x4 (&acc)[16][2],
-                                           int lane) {
-    P.pre<C, LAST>();
-    const u32x4 *w = P.slot<C>();
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        u32x4 a = w[t * 64 + lane];
-        acc[t][0] = mma(a, bop[KB][0], acc[t][0]);
-        acc[t][1] = mma(a, bop[KB][1], acc[t][1]);
-    }
-    __syncthreads();
+// compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1
+template <class F, int... I>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F> __device__ __forceinline__ void sfor(F &&f) {
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int C0, int LAST, int NKB>
-__device__ __forceinline__ void layer_full(Pipe &P, const u32x4 (&bop)[8][2], f32x4 (&acc)[16][2],
-                                           int lane) {
-    chunk_full<C0, LAST, 0>(P, bop, acc, lane);
-    chunk_full<C0 + 1, LAST, 1>(P, bop, acc, lane);
-    chunk_full<C0 + 2, LAST, 2>(P, bop, acc, lane);
-    chunk_full<C0 + 3, LAST, 3>(P, bop, acc, lane);
-    if constexpr (NKB == 8) {
-        chunk_full<C0 + 4, LAST, 4>(P, bop, acc, lane);
-        chunk_full<C0 + 5, LAST, 5>(P, bop, acc, lane);
-        chunk_full<C0 + 6, LAST, 6>(P, bop, acc, lane);
-        chunk_full<C0 + 7, LAST, 7>(P, bop, acc, lane);
-    }
-}
-
-// first-layer backward chunk: K-blocks 2p, 2p+1 x 8 tiles of gamma features
-template <int C, int LAST, int PAIR>
-__device__ __forceinline__ void chunk_w1t(Pipe &P, const u32x4 (&bop)[8][2], f32x4 (&acc)[16][2],
-                                          int lane) {
-    P.pre<C, LAST>();
-    const u32x4 *w = P.slot<C>();
+// One layer in out-tile-major order: tile t's K loop (NKB K-blocks of 32,
+// both query blocks), then the epilogue of tile t-1, so that one tile's
+// elementwise work overlaps the next tile's matrix products.  Chunks hold TPC
+// tiles; chunk C0 + t / TPC.  init(t, acc) sets the accumulator, epi(t, acc)
+// consumes it.
+template <int C0, int LAST, int NT, int NKB, int TPC, int QBN, int NW, class Init, class Epi>
+__device__ __forceinline__ void run_layer(Pipe<NW> &P, const u32x4 (&bin)[8][QBN], int lane,
+                                          Init &&init, Epi &&epi) {
+    // with one wave per SIMD the next tile's fragments are read a tile ahead;
+    // with two, the other wave hides the LDS latency and registers are short
+    constexpr bool AHEAD = QBN > 1;
+    f32x4 acc[2][QBN];
+    u32x4 fr[AHEAD ? 2 : 1][NKB];
+    if constexpr (AHEAD) {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        u32x4 a = w[t * 64 + lane];
-        constexpr int kb0 = 2 * PAIR;
-        const int kb = kb0 + (t >> 3), it = t & 7;
-        acc[it][0] = mma(a, bop[kb][0], acc[it][0]);
-        acc[it][1] = mma(a, bop[kb][1], acc[it][1]);
+        for (int kb = 0; kb < NKB; ++kb) fr[0][kb] = P.template slot<C0>()[kb * 64 + lane];
     }
-    __syncthreads();
-}
-
-__device__ __forceinline__ void init_bias(f32x4 (&acc)[16][2], const float *b, int g) {
+    sfor<NT>([&](auto T) {
+        constexpr int t = decltype(T)::value;
+        constexpr int c = C0 + t / TPC;
+        constexpr int tl = t % TPC;
+        constexpr int cur = AHEAD ? (t & 1) : 0;
+        if constexpr (tl == 0) P.template pre<c, LAST>();
+        if constexpr (AHEAD && t + 1 < NT) {
+            constexpr int c1 = C0 + (t + 1) / TPC, tl1 = (t + 1) % TPC;
+            const u32x4 *w = P.template slot<c1>() + tl1 * NKB * 64 + lane;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        f32x4 v = *(const f32x4 *)(b + 16 * t + 4 * g);
-        acc[t][0] = v;
-        acc[t][1] = v;
-    }
-}
-
-__device__ __forceinline__ void zero_acc(f32x4 (&acc)[16][2]) {
+            for (int kb = 0; kb < NKB; ++kb) fr[(t + 1) & 1][kb] = w[kb * 64];
+            __builtin_amdgcn_sched_barrier(0);   // keep the reads a full tile ahead
+        }
+        if constexpr (!AHEAD) {
+            const u32x4 *w = P.template slot<c>() + tl * NKB * 64 + lane;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t][0] = acc[t][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            for (int kb = 0; kb < NKB; ++kb) fr[0][kb] = w[kb * 64];
+        }
+        init(T, acc[t & 1]);
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+            for (int qb = 0; qb < QBN; ++qb) acc[t & 1][qb] = mma(fr[cur][kb], bin[kb][qb], acc[t & 1][qb]);
+        if constexpr (t > 0) epi(std::integral_constant<int, t - 1>{}, acc[(t - 1) & 1]);
+        if constexpr (tl == TPC - 1) __syncthreads();
+    });
+    epi(std::integral_constant<int, NT - 1>{}, acc[(NT - 1) & 1]);
 }
 
 // scaled silu: s = 1 / (1 + 2^-z'), a' = z' s, silu'(z) = s + a' (1 - s) / log2(e)
@@ -254,61 +258,31 @@ __device__ __forceinline__ void silu_s(float z, float &a, float &d) {
     d = fmaf(a, fmaf(-s, kInvLog2e, kInvLog2e), s);
 }
 
-// hidden-layer epilogue: next B operand from a', stored silu' (BF16 pairs)
-template <bool KEEP>
-__device__ __forceinline__ void epi_hidden(const f32x4 (&acc)[16][2], u32x4 (&bop)[8][2],
-                                           uint32_t (&S)[16][2][2]) {
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
-#pragma unroll
-        for (int qb = 0; qb < 2; ++qb) {
-            float a[4], d[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) silu_s(acc[t][qb][r], a[r], d[r]);
-            bop[t >> 1][qb][(t & 1) * 2] = pk2(a[0], a[1]);
-            bop[t >> 1][qb][(t & 1) * 2 + 1] = pk2(a[2], a[3]);
-            if (KEEP) {
-                S[t][qb][0] = pk2(d[0], d[1]);
-                S[t][qb][1] = pk2(d[2], d[3]);
-            }
-        }
+// tile t of a layer output -> half (t & 1) of K-block t / 2 of the next B operand
+template <int t, int QBN>
+__device__ __forceinline__ void put_b(u32x4 (&b)[8][QBN], int qb, float v0, float v1, float v2, float v3) {
+    b[t >> 1][qb][(t & 1) * 2] = pk2(v0, v1);
+    b[t >> 1][qb][(t & 1) * 2 + 1] = pk2(v2, v3);
 }
 
-// backward epilogue: u = g * silu'(z) of the layer below, as the next B operand
-__device__ __forceinline__ void epi_back(const f32x4 (&acc)[16][2], u32x4 (&bop)[8][2],
-                                         const uint32_t (&S)[16][2][2]) {
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
-#pragma unroll
-        for (int qb = 0; qb < 2; ++qb) {
-            const f32x4 g = acc[t][qb];
-            float u0 = g[0] * bf_lo(S[t][qb][0]), u1 = g[1] * bf_hi(S[t][qb][0]);
-            float u2 = g[2] * bf_lo(S[t][qb][1]), u3 = g[3] * bf_hi(S[t][qb][1]);
-            bop[t >> 1][qb][(t & 1) * 2] = pk2(u0, u1);
-            bop[t >> 1][qb][(t & 1) * 2 + 1] = pk2(u2, u3);
-        }
-}
-
-template <bool GRAD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_mlp(MlpArgs A) {
-    __shared__ u32x4 lds[2 * kChunkU4];
+// QBN 16-query blocks per wave, NW waves per workgroup
+template <bool GRAD, int QBN, int NW>
+__device__ __forceinline__ void mlp_body(const MlpArgs &A, u32x4 *lds) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, li = lane & 15;
     constexpr int LAST = GRAD ? kChunks - 1 : kChunksFwd - 1;
 
-    Pipe P;
+    Pipe<NW> P;
     P.lds = lds;
     P.src = A.frag;
-    P.tid = tid;
-    P.load<0>();
-    P.store<0>();
-    P.load<1>();
-    P.load<2>();
+    P.wave = wave;
+    P.lane = lane;
+    P.template load<0>();
+    P.template load<1>();
 
-    const int64_t q0 = (int64_t)blockIdx.x * kQB + wave * kQW + li;
-    float x[2][3];
+    const int64_t q0 = (int64_t)blockIdx.x * (NW * 16 * QBN) + wave * (16 * QBN) + li;
+    float x[QBN][3];
 #pragma unroll
-    for (int qb = 0; qb < 2; ++qb) {
+    for (int qb = 0; qb < QBN; ++qb) {
         int64_t q = q0 + 16 * qb;
         bool live = q < A.nq;
 #pragma unroll
@@ -317,92 +291,116 @@ k_mlp(MlpArgs A) {
 
     // first-layer input: lane holds gamma features 16 t + 4 g + r, t = 0..7
     // (sines for t < 4, cosines of the same frequencies for t >= 4)
-    u32x4 bop[8][2];
-    {
+    u32x4 bA[8][QBN], bB[8][QBN];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            float s[2][4], c[2][4];
+    for (int t = 0; t < 4; ++t) {
+        float sn[QBN][4], cs[QBN][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float *b = A.Bf + 3 * (16 * t + 4 * g + r);
-                float b0 = b[0], b1 = b[1], b2 = b[2];
+        for (int r = 0; r < 4; ++r) {
+            const float *b = A.Bf + 3 * (16 * t + 4 * g + r);
+            float b0 = b[0], b1 = b[1], b2 = b[2];
 #pragma unroll
-                for (int qb = 0; qb < 2; ++qb) {
-                    float th = fmaf(b0, x[qb][0], fmaf(b1, x[qb][1], b2 * x[qb][2]));
-                    sincos_rev(th, s[qb][r], c[qb][r]);
-                }
+            for (int qb = 0; qb < QBN; ++qb) {
+                float th = fmaf(b0, x[qb][0], fmaf(b1, x[qb][1], b2 * x[qb][2]));
+                sincos_rev(th, sn[qb][r], cs[qb][r]);
             }
+        }
 #pragma unroll
-            for (int qb = 0; qb < 2; ++qb) {
-                // tile t -> K-block t / 2, half t % 2; tile t + 4 -> K-block 2 + t / 2
-                bop[t >> 1][qb][(t & 1) * 2] = pk2(kLog2e * s[qb][0], kLog2e * s[qb][1]);
-                bop[t >> 1][qb][(t & 1) * 2 + 1] = pk2(kLog2e * s[qb][2], kLog2e * s[qb][3]);
-                bop[2 + (t >> 1)][qb][(t & 1) * 2] = pk2(kLog2e * c[qb][0], kLog2e * c[qb][1]);
-                bop[2 + (t >> 1)][qb][(t & 1) * 2 + 1] = pk2(kLog2e * c[qb][2], kLog2e * c[qb][3]);
-            }
+        for (int qb = 0; qb < QBN; ++qb) {
+            bA[t >> 1][qb][(t & 1) * 2] = pk2(kLog2e * sn[qb][0], kLog2e * sn[qb][1]);
+            bA[t >> 1][qb][(t & 1) * 2 + 1] = pk2(kLog2e * sn[qb][2], kLog2e * sn[qb][3]);
+            bA[2 + (t >> 1)][qb][(t & 1) * 2] = pk2(kLog2e * cs[qb][0], kLog2e * cs[qb][1]);
+            bA[2 + (t >> 1)][qb][(t & 1) * 2 + 1] = pk2(kLog2e * cs[qb][2], kLog2e * cs[qb][3]);
         }
     }
     __syncthreads();
 
-    f32x4 acc[16][2];
-    uint32_t S1[16][2][2], S2[16][2][2], S3[16][2][2];
-
-    init_bias(acc, A.bias_s, g);
-    layer_full<0, LAST, 4>(P, bop, acc, lane);
-    epi_hidden<GRAD>(acc, bop, S1);
-    init_bias(acc, A.bias_s + WD, g);
-    layer_full<4, LAST, 8>(P, bop, acc, lane);
-    epi_hidden<GRAD>(acc, bop, S2);
-    init_bias(acc, A.bias_s + 2 * WD, g);
-    layer_full<12, LAST, 8>(P, bop, acc, lane);
-    epi_hidden<GRAD>(acc, bop, S3);
-    init_bias(acc, A.bias_s + 3 * WD, g);
-    layer_full<20, LAST, 8>(P, bop, acc, lane);
-
-    // output layer and the seed of the backward sweep: u4 = (w5 / log2 e) silu'(z4)
-    float y[2] = {0.f, 0.f};
+    uint32_t S1[16][QBN][2], S2[16][QBN][2], S3[16][QBN][2];
+    auto bias_init = [&](const float *bias) {
+        return [=](auto T, f32x4(&acc)[QBN]) {
+            constexpr int t = decltype(T)::value;
+            f32x4 v = *(const f32x4 *)(bias + 16 * t + 4 * g);
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
+            for (int qb = 0; qb < QBN; ++qb) acc[qb] = v;
+        };
+    };
+    auto zero_init = [](auto, f32x4(&acc)[QBN]) {
+#pragma unroll
+        for (int qb = 0; qb < QBN; ++qb) acc[qb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    };
+    // hidden layer epilogue: next B operand from a', silu' kept for the backward sweep
+    auto hidden = [&](u32x4(&bo)[8][QBN], uint32_t(&S)[16][QBN][2]) {
+        return [&](auto T, const f32x4(&acc)[QBN]) {
+            constexpr int t = decltype(T)::value;
+#pragma unroll
+            for (int qb = 0; qb < QBN; ++qb) {
+                float a[4], d[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) silu_s(acc[qb][r], a[r], d[r]);
+                put_b<t, QBN>(bo, qb, a[0], a[1], a[2], a[3]);
+                if (GRAD) {
+                    S[t][qb][0] = pk2(d[0], d[1]);
+                    S[t][qb][1] = pk2(d[2], d[3]);
+                }
+            }
+        };
+    };
+
+    run_layer<0, LAST, 16, 4, 8, QBN>(P, bA, lane, bias_init(A.bias_s), hidden(bB, S1));
+    run_layer<2, LAST, 16, 8, 4, QBN>(P, bB, lane, bias_init(A.bias_s + WD), hidden(bA, S2));
+    run_layer<6, LAST, 16, 8, 4, QBN>(P, bA, lane, bias_init(A.bias_s + 2 * WD), hidden(bB, S3));
+
+    // last hidden layer: output y = (w5 / log2 e) . a'_4 + b5 and the seed of
+    // the backward sweep u4 = (w5 / log2 e) silu'(z4)
+    float y[QBN];
+#pragma unroll
+    for (int qb = 0; qb < QBN; ++qb) y[qb] = 0.f;
+    run_layer<10, LAST, 16, 8, 4, QBN>(P, bB, lane, bias_init(A.bias_s + 3 * WD), [&](auto T, const f32x4(&acc)[QBN]) {
+        constexpr int t = decltype(T)::value;
         f32x4 w = *(const f32x4 *)(A.w5s + 16 * t + 4 * g);
 #pragma unroll
-        for (int qb = 0; qb < 2; ++qb) {
+        for (int qb = 0; qb < QBN; ++qb) {
             float a[4], d[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                silu_s(acc[t][qb][r], a[r], d[r]);
+                silu_s(acc[qb][r], a[r], d[r]);
                 y[qb] = fmaf(a[r], w[r], y[qb]);
             }
-            if (GRAD) {
-                bop[t >> 1][qb][(t & 1) * 2] = pk2(w[0] * d[0], w[1] * d[1]);
-                bop[t >> 1][qb][(t & 1) * 2 + 1] = pk2(w[2] * d[2], w[3] * d[3]);
-            }
+            if (GRAD) put_b<t, QBN>(bA, qb, w[0] * d[0], w[1] * d[1], w[2] * d[2], w[3] * d[3]);
         }
-    }
+    });
 #pragma unroll
-    for (int qb = 0; qb < 2; ++qb) {
+    for (int qb = 0; qb < QBN; ++qb) {
         y[qb] += __shfl_xor(y[qb], 16);
         y[qb] += __shfl_xor(y[qb], 32);
         y[qb] += *A.b5;
     }
 
-    float gx[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float gx[QBN][3];
+#pragma unroll
+    for (int qb = 0; qb < QBN; ++qb) gx[qb][0] = gx[qb][1] = gx[qb][2] = 0.f;
     if constexpr (GRAD) {
-        zero_acc(acc);
-        layer_full<28, LAST, 8>(P, bop, acc, lane);   // through W4
-        epi_back(acc, bop, S3);
-        zero_acc(acc);
-        layer_full<36, LAST, 8>(P, bop, acc, lane);   // through W3
-        epi_back(acc, bop, S2);
-        zero_acc(acc);
-        layer_full<44, LAST, 8>(P, bop, acc, lane);   // through W2
-        epi_back(acc, bop, S1);
-        zero_acc(acc);
-        chunk_w1t<52, LAST, 0>(P, bop, acc, lane);    // through W1
-        chunk_w1t<53, LAST, 1>(P, bop, acc, lane);
-        chunk_w1t<54, LAST, 2>(P, bop, acc, lane);
-        chunk_w1t<55, LAST, 3>(P, bop, acc, lane);
-        // acc[it] holds dy/d(a'_0) for gamma features 16 it + 4 g + r;
-        // dy/dgamma = log2(e) acc; chain through sin and cos of 2 pi b.x
+        // backward: u_{l-1} = (W_l^T u_l) silu'(z_{l-1})
+        auto back = [&](u32x4(&bo)[8][QBN], const uint32_t(&S)[16][QBN][2]) {
+            return [&](auto T, const f32x4(&acc)[QBN]) {
+                constexpr int t = decltype(T)::value;
+#pragma unroll
+                for (int qb = 0; qb < QBN; ++qb)
+                    put_b<t, QBN>(bo, qb, acc[qb][0] * bf_lo(S[t][qb][0]), acc[qb][1] * bf_hi(S[t][qb][0]),
+                             acc[qb][2] * bf_lo(S[t][qb][1]), acc[qb][3] * bf_hi(S[t][qb][1]));
+            };
+        };
+        run_layer<14, LAST, 16, 8, 4, QBN>(P, bA, lane, zero_init, back(bB, S3));   // through W4
+        run_layer<18, LAST, 16, 8, 4, QBN>(P, bB, lane, zero_init, back(bA, S2));   // through W3
+        run_layer<22, LAST, 16, 8, 4, QBN>(P, bA, lane, zero_init, back(bB, S1));   // through W2
+        // through W1: dy/d(a'_0) for the 128 gamma features, all tiles kept
+        f32x4 g0[8][QBN];
+        run_layer<26, LAST, 8, 8, 4, QBN>(P, bB, lane, zero_init, [&](auto T, const f32x4(&acc)[QBN]) {
+            constexpr int t = decltype(T)::value;
+#pragma unroll
+            for (int qb = 0; qb < QBN; ++qb) g0[t][qb] = acc[qb];
+        });
+        // dy/dgamma = log2(e) g0; chain through sin and cos of 2 pi b.x
         const float cg = kLog2e * 6.283185307179586f;
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -411,18 +409,18 @@ k_mlp(MlpArgs A) {
                 const float *b = A.Bf + 3 * (16 * t + 4 * g + r);
                 float b0 = b[0], b1 = b[1], b2 = b[2];
 #pragma unroll
-                for (int qb = 0; qb < 2; ++qb) {
-                    float s, c;
+                for (int qb = 0; qb < QBN; ++qb) {
+                    float sn, cs;
                     float th = fmaf(b0, x[qb][0], fmaf(b1, x[qb][1], b2 * x[qb][2]));
-                    sincos_rev(th, s, c);
-                    float k = cg * (acc[t][qb][r] * c - acc[t + 4][qb][r] * s);
+                    sincos_rev(th, sn, cs);
+                    float k = cg * (g0[t][qb][r] * cs - g0[t + 4][qb][r] * sn);
                     gx[qb][0] = fmaf(k, b0, gx[qb][0]);
                     gx[qb][1] = fmaf(k, b1, gx[qb][1]);
                     gx[qb][2] = fmaf(k, b2, gx[qb][2]);
                 }
             }
 #pragma unroll
-        for (int qb = 0; qb < 2; ++qb)
+        for (int qb = 0; qb < QBN; ++qb)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 gx[qb][a] += __shfl_xor(gx[qb][a], 16);
@@ -432,7 +430,7 @@ k_mlp(MlpArgs A) {
 
     if (g == 0) {
 #pragma unroll
-        for (int qb = 0; qb < 2; ++qb) {
+        for (int qb = 0; qb < QBN; ++qb) {
             int64_t q = q0 + 16 * qb;
             if (q >= A.nq) continue;
             if (A.d_out) A.d_out[q] = y[qb];
@@ -445,6 +443,43 @@ k_mlp(MlpArgs A) {
             if (A.err_out) A.err_out[q] = fabsf(y[qb] - A.label[q]);
         }
     }
+}
+
+// Launch shapes: queries per wave = 16 x QB, waves per workgroup, waves per
+// SIMD the register budget allows.
+#ifndef SD_MLP_GRAD_QB
+#define SD_MLP_GRAD_QB 1
+#endif
+#ifndef SD_MLP_GRAD_NW
+#define SD_MLP_GRAD_NW 8
+#endif
+#ifndef SD_MLP_GRAD_WPE
+#define SD_MLP_GRAD_WPE 2
+#endif
+#ifndef SD_MLP_VAL_QB
+#define SD_MLP_VAL_QB 1
+#endif
+#ifndef SD_MLP_VAL_NW
+#define SD_MLP_VAL_NW 8
+#endif
+#ifndef SD_MLP_VAL_WPE
+#define SD_MLP_VAL_WPE 2
+#endif
+constexpr int kGradQ = 16 * SD_MLP_GRAD_QB * SD_MLP_GRAD_NW;   // queries per workgroup
+constexpr int kValQ = 16 * SD_MLP_VAL_QB * SD_MLP_VAL_NW;
+
+__global__ void __launch_bounds__(64 * SD_MLP_GRAD_NW)
+__attribute__((amdgpu_waves_per_eu(SD_MLP_GRAD_WPE, SD_MLP_GRAD_WPE)))
+k_mlp_grad(MlpArgs A) {
+    __shared__ u32x4 lds[kSlots * kChunkU4];
+    mlp_body<true, SD_MLP_GRAD_QB, SD_MLP_GRAD_NW>(A, lds);
+}
+
+__global__ void __launch_bounds__(64 * SD_MLP_VAL_NW)
+__attribute__((amdgpu_waves_per_eu(SD_MLP_VAL_WPE, SD_MLP_VAL_WPE)))
+k_mlp_value(MlpArgs A) {
+    __shared__ u32x4 lds[kSlots * kChunkU4];
+    mlp_body<false, SD_MLP_VAL_QB, SD_MLP_VAL_NW>(A, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,9 +749,12 @@ int launch_mlp(const sd_surrogate *h, const float *Q, int64_t nq, float *d, floa
     A.band = band;
     A.label = label;
     A.err_out = err;
-    unsigned grid = (unsigned)((nq + kQB - 1) / kQB);
-    if (gr) hipLaunchKernelGGL(k_mlp<true>, dim3(grid), dim3(256), 0, s, A);
-    else hipLaunchKernelGGL(k_mlp<false>, dim3(grid), dim3(256), 0, s, A);
+    if (gr)
+        hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)((nq + kGradQ - 1) / kGradQ)), dim3(64 * SD_MLP_GRAD_NW),
+                           0, s, A);
+    else
+        hipLaunchKernelGGL(k_mlp_value, dim3((unsigned)((nq + kValQ - 1) / kValQ)), dim3(64 * SD_MLP_VAL_NW),
+                           0, s, A);
     SD_HIP(hipGetLastError());
     return SD_OK;
 }

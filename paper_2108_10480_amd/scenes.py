@@ -228,8 +228,11 @@ def surrogate_param_shapes():
 
 
 def fourier_matrix(seed=11, sigma=2.0, n_freq=SURR_N_FREQ):
-    """Random Fourier frequencies B ~ N(0, sigma^2), n_freq x 3, float32."""
-    return _f32(np.random.default_rng(seed).normal(0.0, sigma, (n_freq, 3)))
+    """Random Fourier frequencies B ~ N(0, sigma^2), n_freq x 3, float32.
+    sigma may be a sequence: equal groups of rows use each scale."""
+    rng = np.random.default_rng(seed)
+    sig = np.repeat(np.atleast_1d(np.asarray(sigma, np.float64)), -(-n_freq // np.size(sigma)))[:n_freq]
+    return _f32(rng.normal(0.0, 1.0, (n_freq, 3)) * sig[:, None])
 
 
 def surrogate_init(seed=12):

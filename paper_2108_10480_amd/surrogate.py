@@ -126,11 +126,15 @@ def sd_eval_surrogate(scene, sur, Q, alpha, beta=0.5, band=0.05, alpha_u=0.0, fl
     return d, g, r, nfb.value
 
 
-def cosine_lr(step, total, lr0, lr_min):
-    return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * min(step, total) / max(total, 1)))
+def cosine_lr(step, total, lr0, lr_min, warmup=0):
+    """Linear warm-up over `warmup` steps, then cosine decay to lr_min."""
+    if step < warmup:
+        return lr0 * (step + 1) / warmup
+    t = (step - warmup) / max(total - warmup, 1)
+    return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * min(t, 1.0)))
 
 
-def train(sur, X, labels, epochs, batch=65536, lr0=1e-3, lr_min=1e-5, seed=13, log_every=0):
+def train(sur, X, labels, epochs, batch=65536, lr0=3e-3, lr_min=1e-5, seed=13, log_every=0, warmup=0):
     """Adam over `epochs` passes of (X, labels) (device tensors) in seeded
     shuffled order; returns the per-step losses (host array)."""
     n = X.shape[0]
@@ -144,7 +148,7 @@ def train(sur, X, labels, epochs, batch=65536, lr0=1e-3, lr_min=1e-5, seed=13, l
         order = torch.as_tensor(scenes.epoch_order(n, ep, seed), device=X.device)
         base = order.data_ptr()
         for b in range(steps_per_epoch):
-            lr = cosine_lr(k, total, lr0, lr_min)
+            lr = cosine_lr(k, total, lr0, lr_min, warmup)
             sur.train_step(X, labels, base + 4 * b * batch, batch, lr, losses.data_ptr() + 4 * k)
             k += 1
         if log_every and (ep + 1) % log_every == 0:
