@@ -620,6 +620,7 @@ k_colsum(const T *__restrict__ src, int cols, int64_t rows, int64_t rows_per_chu
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
     const int64_t r1 = min(rows, r0 + rows_per_chunk);
     float s = 0.f;
+#pragma unroll 8
     for (int64_t r = r0; r < r1; ++r) {
         float v = (float)src[r * cols + c];
         s = scale ? fmaf(scale[r * scale_ld], v, s) : s + v;
@@ -633,6 +634,7 @@ __global__ void k_reduce_chunks(const float *__restrict__ part, int chunks, int6
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= len) return;
     float s = 0.f;
+#pragma unroll 8
     for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * ld + i];
     out[i] = s * scale;
 }
@@ -711,6 +713,7 @@ namespace sd {
 namespace {
 
 constexpr int kSplitRows = 2048;   // split-K length of the weight-gradient products
+constexpr int kSumRows = 256;      // rows per partial of the column sums (bias gradients)
 
 int sur_alloc(sd_surrogate *h, void **p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
@@ -818,20 +821,20 @@ int loss_grad(sd_surrogate *h, const float *X, const float *y, int64_t n_rows, c
         hipLaunchKernelGGL(k_reduce_chunks, dim3(blocks(len)), dim3(256), 0, s, h->part, splits, len,
                            len, h->grad + off_W(l), 1.f);
         // bias: column sums of G_l
-        int64_t chunks = (n + kSplitRows - 1) / kSplitRows;
+        int64_t chunks = (n + kSumRows - 1) / kSumRows;
         hipLaunchKernelGGL(k_colsum<__bf16>, dim3((unsigned)chunks), dim3(256), 0, s, h->Gr[l - 1], WD, n,
-                           (int64_t)kSplitRows, (const float *)nullptr, 0, h->part);
+                           (int64_t)kSumRows, (const float *)nullptr, 0, h->part);
         hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, s, h->part, (int)chunks, (int64_t)WD,
                            (int64_t)WD, h->grad + off_b(l), 1.f);
     }
     // output layer: dw5 = sum dy a4, db5 = sum dy; loss = mean r^2
-    int64_t chunks = (n + kSplitRows - 1) / kSplitRows;
+    int64_t chunks = (n + kSumRows - 1) / kSumRows;
     hipLaunchKernelGGL(k_colsum<float>, dim3((unsigned)chunks), dim3(256), 0, s, h->A4f, WD, n,
-                       (int64_t)kSplitRows, h->dyr, 2, h->part);
+                       (int64_t)kSumRows, h->dyr, 2, h->part);
     hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, s, h->part, (int)chunks, (int64_t)WD,
                        (int64_t)WD, h->grad + OFF_W5, 1.f);
     hipLaunchKernelGGL(k_colsum<float>, dim3((unsigned)chunks), dim3(256), 0, s, h->dyr, 2, n,
-                       (int64_t)kSplitRows, (const float *)nullptr, 0, h->part);
+                       (int64_t)kSumRows, (const float *)nullptr, 0, h->part);
     hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, s, h->part, (int)chunks, (int64_t)1,
                        (int64_t)2, h->grad + OFF_B5, 1.f);
     hipLaunchKernelGGL(k_reduce_chunks, dim3(1), dim3(256), 0, s, h->part + 1, (int)chunks, (int64_t)1,
@@ -885,7 +888,7 @@ extern "C" int sd_surrogate_create(const float *B_host, const float *theta_host,
         if (!rc) rc = fl(&h->A4f, nb * WD);
         if (!rc) rc = fl(&h->dyr, 2 * nb);
         const int64_t splits = (max_batch + kSplitRows - 1) / kSplitRows;
-        h->part_len = splits * (int64_t)WD * WD;
+        h->part_len = std::max(splits * (int64_t)WD * WD, (max_batch + kSumRows - 1) / kSumRows * (int64_t)WD);
         if (!rc) rc = fl(&h->part, (size_t)h->part_len);
     }
     if (!rc) {

@@ -263,3 +263,85 @@ def surrogate_samples(scene, n, seed=6, near_frac=0.7, offset=0.5, box=1.5):
 def epoch_order(n, epoch, seed=13):
     """Shuffled sample order of one training epoch, int32."""
     return _i32(np.random.default_rng([seed, epoch]).permutation(n))
+
+
+# --------------------------------------------------------------------------
+# mixed co-dimensional street scene with a rigid body (differentiation workload)
+# --------------------------------------------------------------------------
+def street_scene(scale=1.0, seed=0):
+    """Synthetic lidar street (metres; x in [0, 100], y in [-10, 10]) with every
+    primitive class: ground points (z ~ N(0, 0.01^2)), 50 poles sampled as point
+    columns (radius 0.1, height 8), two rows of box buildings whose facades are
+    sampled on a 5 cm grid with 20 % dropout, four catenary wires through the
+    pole tops (polylines, 5,000 segments each), and a 250 x 100 torus (R = 1,
+    r = 0.35; 50,000 triangles) resting at (50, 0, 2).  At scale = 1 the point
+    cloud holds exactly 2,000,000 points; smaller scales shrink every count.
+    Returns (Scene, body_vertices) with the body in its own frame."""
+    rng = np.random.default_rng(seed)
+    n_ground = int(round(1_000_000 * scale))
+    n_pole = max(int(round(2000 * scale)), 8)
+    n_total = int(round(2_000_000 * scale))
+    ground = np.stack([rng.uniform(0, 100, n_ground), rng.uniform(-10, 10, n_ground),
+                       rng.normal(0, 0.01, n_ground)], 1)
+    poles = []
+    for k in range(50):
+        th = rng.uniform(0, 2 * np.pi, n_pole)
+        poles.append(np.stack([1 + 2 * k + 0.1 * np.cos(th), 8 + 0.1 * np.sin(th),
+                               rng.uniform(0, 8, n_pole)], 1))
+    poles = np.concatenate(poles)
+    # building rows: 10 buildings of 10 m along x per row, heights U[6, 14];
+    # facades at |y| = 10 and |y| = 14, 5 cm grid (coarser when scale < 1)
+    h = 0.05 / np.sqrt(max(scale, 1e-6)) if scale < 1 else 0.05
+    heights = rng.uniform(6, 14, (2, 10))
+    fac = []
+    for row, sgn in enumerate((1.0, -1.0)):
+        for b in range(10):
+            xs = np.arange(10 * b, 10 * b + 10, h) + 0.5 * h
+            zs = np.arange(0, heights[row, b], h) + 0.5 * h
+            gx, gz = np.meshgrid(xs, zs, indexing="ij")
+            for yy in (10.0, 14.0):
+                fac.append(np.stack([gx.ravel(), np.full(gx.size, sgn * yy), gz.ravel()], 1))
+    fac = np.concatenate(fac)
+    fac = fac[rng.random(len(fac)) < 0.8]
+    need = n_total - n_ground - len(poles)
+    fac = fac[rng.permutation(len(fac))[:max(need, 0)]]
+    pts = np.concatenate([ground, poles, fac])
+    # wires: catenaries z = z0 + c (cosh((x - xm)/c) - 1) - sag between consecutive
+    # pole tops, 4 heights, 5,000 segments each along x in [1, 99]
+    n_seg = max(int(round(5000 * scale)), 50)
+    wires_v, wires_e = [], []
+    base = len(pts)
+    for z0 in (7.4, 7.6, 7.8, 8.0):
+        x = np.linspace(1, 99, n_seg + 1)
+        span = 2.0
+        xm = 1 + span * (np.floor((x - 1) / span) + 0.5)
+        c = 5.0
+        z = z0 + c * (np.cosh((x - xm) / c) - 1) - c * (np.cosh(span / 2 / c) - 1)
+        v = np.stack([x, np.full_like(x, 8.0), z], 1)
+        e = np.stack([np.arange(n_seg), np.arange(n_seg) + 1], 1) + base
+        wires_v.append(v)
+        wires_e.append(e)
+        base += len(v)
+    wv = np.concatenate(wires_v)
+    we = np.concatenate(wires_e)
+    nu, nv = (250, 100) if scale >= 1 else (max(int(250 * np.sqrt(scale)), 12), max(int(100 * np.sqrt(scale)), 6))
+    body, F = torus_grid(nu, nv, 1.0, 0.35)
+    tv = body + np.array([50.0, 0.0, 2.0])
+    V = np.concatenate([pts, wv, tv])
+    T = F + base
+    sc = Scene(V=_f32(V), P=_i32(np.arange(len(pts))), E=_i32(we), T=_i32(T), name=f"street_{scale:g}")
+    return sc, _f32(body)
+
+
+def rigid_transforms(K, seed=5, lo=(5.0, -8.0, 0.2), hi=(95.0, 8.0, 6.0)):
+    """K random rigid transforms: rotations from unit quaternions, translations
+    uniform in the box [lo, hi]; R (K, 3, 3) and t (K, 3), float32."""
+    rng = np.random.default_rng(seed)
+    q = rng.normal(size=(K, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    R = np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                  2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                  2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], 1)
+    t = rng.uniform(lo, hi, (K, 3))
+    return _f32(R.reshape(K, 3, 3)), _f32(t)
