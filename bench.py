@@ -73,6 +73,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate comparison")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid-body street workload")
     ap.add_argument("--rigid-steps", type=int, default=5)
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the alpha / precision sweep on the terrain + mesh scene")
+    ap.add_argument("--sweep-scale", type=float, default=0.1,
+                    help="size of the sweep scene relative to 20M points, 1M triangles, 200k edges, 32M queries")
     ap.add_argument("--sur-train", type=int, default=20_000_000, help="surrogate training samples")
     ap.add_argument("--sur-epochs", type=int, default=40)
     ap.add_argument("--sur-nq", type=int, default=16_000_000, help="surrogate inference queries")
@@ -253,7 +257,75 @@ def main():
         out["surrogate"] = surrogate_leg(args, sc, scene, np, torch, api, scenes)
     if not args.no_rigid:
         out["rigid"] = rigid_leg(args, np, torch, api, scenes)
+    if args.sweep:
+        out["precision_sweep"] = sweep_leg(args, np, torch, api, scenes)
     print(json.dumps(out))
+
+
+def sweep_leg(args, np, torch, api, scenes):
+    """Alpha sweep on the terrain + mesh scene: throughput, and error against
+    the FP64 oracle (Barnes-Hut on the exported hierarchies) of the plain FP32
+    path and of the FP64 final logarithm, for alpha = 10, 100, 1000, 5000."""
+    beta = 0.5
+    sc = scenes.terrain_scene(args.sweep_scale)
+    t0 = time.perf_counter()
+    scene = api.upload_scene(sc)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    nq = max(int(32_000_000 * args.sweep_scale), 1000)
+    Q = torch.as_tensor(scenes.terrain_queries(sc, nq, seed=10), device="cuda")
+    perm = torch.empty(nq, dtype=torch.int32, device="cuda")
+    d = torch.empty(nq, device="cuda")
+    g = torch.empty((nq, 3), device="cuda")
+    n_or = min(20000, nq)
+    Qs = Q[:n_or].contiguous()
+    res = {"workload": f"terrain {sc.counts()[0]} points + torus {sc.counts()[2]} triangles + "
+                       f"hemisphere net {sc.counts()[1]} edges; {nq} queries in the box enlarged by 10 %, "
+                       f"beta={beta:g}; oracle subset: first {n_or} queries",
+           "build_ms": build_ms, "alphas": {}}
+    have_oracle = not args.no_cpu_baseline
+    if have_oracle:
+        from oracle import oracle as O
+        osc = O.OracleScene(sc.V, P=sc.P, E=sc.E, T=sc.T)
+        trees = [O.OracleTree(*api.sd_export_bvh(scene, c)) for c in range(3)]
+        lo, hi = scenes.scene_aabb(sc)
+        floor = 1e-3 * float(np.linalg.norm(hi - lo))
+    for alpha in (10.0, 100.0, 1000.0, 5000.0):
+        row = {}
+        for mode, fl in (("fp32", 0), ("fp64_root_log", api.SD_ROOTLOG_F64)):
+            def run():
+                api.sd_query_order(scene, Q, out=perm)
+                api.sd_eval_grad_ordered(scene, Q, perm, alpha, beta, flags=fl, out=d, grad_out=g)
+            run()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                run()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / 3
+            entry = {"queries_per_s": nq / (ms * 1e-3), "ms": ms}
+            if have_oracle:
+                dn, _ = api.sd_eval_grad(scene, Qs, alpha, beta, flags=fl | api.SD_NO_CONSERVATIVE_ROUNDING)
+                dc, _ = api.sd_eval_grad(scene, Qs, alpha, beta, flags=fl)
+                row.setdefault("_gpu", {})[mode] = (dn.cpu().numpy(), dc.cpu().numpy())
+            row[mode] = entry
+        if have_oracle:
+            Qh = Qs.cpu().numpy().astype(np.float64)
+            if "dmin" not in res:
+                res["dmin"] = O.dmin(osc, Qh)
+            dr, _, st = O.barnes_hut(osc, trees, Qh, alpha, beta)
+            ok = st[:, 0] > 1e-6
+            for mode, (dn, dc) in row.pop("_gpu").items():
+                e = O.value_error(dn, dr, floor, res["dmin"])[ok]
+                row[mode]["max_err_vs_oracle"] = float(e.max())
+                row[mode]["median_err_vs_oracle"] = float(np.median(e))
+                row[mode]["conservative_violations"] = int(np.sum(dc[ok] > dr[ok]))
+            row["oracle_n"] = int(ok.sum())
+        res["alphas"][f"{alpha:g}"] = row
+    res.pop("dmin", None)
+    return res
 
 
 def rigid_leg(args, np, torch, api, scenes):

@@ -345,3 +345,74 @@ def rigid_transforms(K, seed=5, lo=(5.0, -8.0, 0.2), hi=(95.0, 8.0, 6.0)):
                   2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], 1)
     t = rng.uniform(lo, hi, (K, 3))
     return _f32(R.reshape(K, 3, 3)), _f32(t)
+
+
+# --------------------------------------------------------------------------
+# terrain + mesh scene for the alpha / precision sweep
+# --------------------------------------------------------------------------
+def _gradient_noise_2d(x, y, rng, period=256):
+    """Seeded 2D gradient (Perlin-style) noise: random unit gradients on an
+    integer lattice, quintic fade, bilinear blend of the corner dot products."""
+    ang = rng.uniform(0, 2 * np.pi, (period, period))
+    gx, gy = np.cos(ang), np.sin(ang)
+    xi, yi = np.floor(x).astype(np.int64), np.floor(y).astype(np.int64)
+    fx, fy = x - xi, y - yi
+    fade = lambda t: t * t * t * (t * (6 * t - 15) + 10)
+    u, v = fade(fx), fade(fy)
+    out = 0.0
+    for dx in (0, 1):
+        for dy in (0, 1):
+            ix, iy = (xi + dx) % period, (yi + dy) % period
+            dot = gx[ix, iy] * (fx - dx) + gy[ix, iy] * (fy - dy)
+            wgt = (u if dx else 1 - u) * (v if dy else 1 - v)
+            out = out + wgt * dot
+    return out
+
+
+def terrain_scene(scale=1.0, seed=9):
+    """Heightfield point cloud over [-1, 1]^2 (z = 0.25 sum_{o<6} 0.5^o
+    n(2^o 2 (x, y)) with seeded gradient noise n, plus N(0, 0.005^2)), a torus
+    (R = 0.5, r = 0.15, axis z, centred at (0, 0, 0.7)) and a hemispherical
+    latitude-longitude net of edges (radius 0.4, centred at (-0.5, 0.5, 0.3)).
+    At scale = 1: 20M points, 1M triangles (1000 x 500 grid), about 200,000
+    edges; smaller scales shrink every count."""
+    rng = np.random.default_rng(seed)
+    n = max(int(round(20_000_000 * scale)), 100)
+    x, y = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    z = np.zeros(n)
+    noise_rng = np.random.default_rng(seed + 1000)
+    for o in range(6):
+        f = 2.0 ** o * 2.0
+        z += 0.25 * 0.5 ** o * _gradient_noise_2d(f * x + 37.0, f * y + 91.0, noise_rng)
+    z += rng.normal(0, 0.005, n)
+    pts = np.stack([x, y, z], 1)
+    k = np.sqrt(scale)
+    tv, tf = torus_grid(max(int(round(1000 * k)), 8), max(int(round(500 * k)), 4), 0.5, 0.15)
+    tv = tv + np.array([0.0, 0.0, 0.7])
+    n_lat = max(int(round(250 * k)), 4)
+    n_lon = max(int(round(400 * k)), 8)
+    th = np.linspace(0, 0.5 * np.pi, n_lat, endpoint=False)       # from the pole down to the rim
+    ph = 2 * np.pi * np.arange(n_lon) / n_lon
+    T_, P_ = np.meshgrid(th[1:], ph, indexing="ij")
+    hv = np.stack([np.sin(T_) * np.cos(P_), np.sin(T_) * np.sin(P_), np.cos(T_)], -1).reshape(-1, 3)
+    hv = np.concatenate([[[0.0, 0.0, 1.0]], hv]) * 0.4 + np.array([-0.5, 0.5, 0.3])
+    idx = lambda i, j: 1 + i * n_lon + (j % n_lon)
+    E = [[0, idx(0, j)] for j in range(n_lon)]
+    for i in range(n_lat - 1):
+        for j in range(n_lon):
+            E.append([idx(i, j), idx(i, j + 1)])
+            if i + 1 < n_lat - 1:
+                E.append([idx(i, j), idx(i + 1, j)])
+    E = np.asarray(E, np.int64)
+    V = np.concatenate([pts, tv, hv])
+    sc = Scene(V=_f32(V), P=_i32(np.arange(n)), E=_i32(E + n + len(tv)), T=_i32(tf + n),
+               name=f"terrain_{scale:g}")
+    return sc
+
+
+def terrain_queries(scene, n, seed=10, grow=0.1):
+    """Queries uniform in the scene's bounding box enlarged by `grow` of its
+    extent on every side."""
+    lo, hi = scene_aabb(scene)
+    ext = hi - lo
+    return uniform_queries(n, seed, lo - grow * ext, hi + grow * ext)

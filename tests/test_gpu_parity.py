@@ -321,3 +321,25 @@ def test_huge_alpha_is_finite():
         # App. A with unit weights: d_min - log|F|/alpha <= d (brute force, beta = 0);
         # the Barnes-Hut bound divides d_min by (1 + beta)
         assert np.all(d >= dm / (1 + beta) - np.log(500) / 5e4 - 1e-5)
+
+
+@pytest.mark.parametrize("alpha", [10.0, 100.0, 1000.0, 5000.0])
+def test_alpha_sweep_terrain_both_precision_modes(alpha):
+    """Terrain points + torus + hemisphere net across the alpha range: the
+    plain FP32 path and the FP64 final logarithm both match the oracle, and the
+    default (rounded) results are conservative."""
+    require_gpu()
+    sc = scenes.terrain_scene(scale=0.002, seed=9)
+    scene = api.upload_scene(sc)
+    Q = scenes.terrain_queries(sc, 3000, seed=10)
+    Qd = cuda(Q)
+    osc = oracle_scene(sc)
+    dr, gr, st = O.barnes_hut(osc, oracle_trees(scene), Q.astype(np.float64), alpha, 0.5)
+    dm = O.dmin(osc, Q.astype(np.float64))
+    ok = st[:, 0] > CUT_TIE
+    for fl in (0, api.SD_ROOTLOG_F64):
+        d, g = api.sd_eval_grad(scene, Qd, alpha, 0.5, flags=fl | api.SD_NO_CONSERVATIVE_ROUNDING)
+        compare(d.cpu().numpy(), g.cpu().numpy(), dr, gr, floor_of(sc), mask=ok, what=f"alpha {alpha} flags {fl}",
+                dmin=dm)
+        dc, _ = api.sd_eval_grad(scene, Qd, alpha, 0.5, flags=fl)
+        assert np.all(dc.cpu().numpy()[ok] <= dr[ok])
