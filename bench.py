@@ -473,14 +473,33 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
         api.sd_query_order(scene, Xin, out=perm)
         api.sd_eval_grad_ordered(scene, Xin, perm, alpha, beta, out=de, grad_out=ge)
 
-    ms_sur = timed(sur_path)
     ms_bh = timed(bh_path)
     ms_mlp = timed(lambda: sur.forward(Xin, grad=True))
-    _, _, _, nfb = S.sd_eval_surrogate(scene, sur, Xin, alpha, beta, band=band, out=d, grad_out=g, routed=routed)
-    torch.cuda.synchronize()
-    keep = routed == 0
-    e_out = (d - de).abs()[keep]
-    e_routed = (d - de).abs()[~keep]
+
+    def routed_run():
+        ms = timed(sur_path)
+        _, _, _, nfb = S.sd_eval_surrogate(scene, sur, Xin, alpha, beta, band=band, out=d, grad_out=g,
+                                           routed=routed)
+        torch.cuda.synchronize()
+        keep = routed == 0
+        e_out = (d - de).abs()[keep]
+        e_routed = (d - de).abs()[~keep]
+        return ms, nfb, keep, {
+            "fallback_fraction": nfb / n,
+            "value_surrogate_path": n / (ms * 1e-3),
+            "speedup_vs_barnes_hut": ms_bh / ms,
+            "ms_surrogate_path": ms,
+            "vs_exact_outside_band": ({"max_abs_err": float(e_out.max()),
+                                       "p99_abs_err": float(torch.quantile(e_out[:1_000_000], 0.99)),
+                                       "gate_1e-3_met": bool(float(e_out.max()) <= 1e-3)}
+                                      if e_out.numel() else {"max_abs_err": None, "note": "every query routed"}),
+            "routed_vs_exact_max_abs_diff": float(e_routed.max()) if e_routed.numel() else 0.0,
+        }
+
+    # global certificate (one margin everywhere), then a local one (32^3 cells)
+    ms_sur, nfb, keep, glob = routed_run()
+    eps_local = sur.certify_cells(Xva, yva, lo=(-1.5, -1.5, -1.5), hi=(1.5, 1.5, 1.5), grid=32, safety=1.5)
+    _, _, keep_local, loc = routed_run()
     flops = n * 2.0 * (SUR_FWD_MACS + SUR_BWD_MACS)
     res = {
         "workload": f"same scene, {n} queries uniform in [-1.5,1.5]^3, alpha={alpha:g}, beta={beta:g}, "
@@ -494,17 +513,11 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
         "validation": {"n": int(Xva.shape[0]), "max_abs_err": float(verr.max()),
                        "rmse": float((verr ** 2).mean().sqrt()),
                        "p99_abs_err": float(torch.quantile(verr[:1_000_000], 0.99))},
-        "fallback_fraction": nfb / n,
-        "value_surrogate_path": n / (ms_sur * 1e-3),
-        "value_barnes_hut": n / (ms_bh * 1e-3),
         "unit": "queries/s",
-        "speedup": ms_bh / ms_sur,
-        "ms": {"surrogate_path": ms_sur, "barnes_hut": ms_bh, "mlp_value_grad": ms_mlp},
-        "vs_exact_outside_band": ({"max_abs_err": float(e_out.max()),
-                                   "p99_abs_err": float(torch.quantile(e_out[:1_000_000], 0.99)),
-                                   "gate_1e-3_met": bool(float(e_out.max()) <= 1e-3)}
-                                  if e_out.numel() else {"max_abs_err": None, "note": "every query routed"}),
-        "routed_vs_exact_max_abs_diff": float(e_routed.max()) if e_routed.numel() else 0.0,
+        "value_barnes_hut": n / (ms_bh * 1e-3),
+        "ms": {"barnes_hut": ms_bh, "mlp_value_grad": ms_mlp},
+        "global_certificate": glob,
+        "local_certificate": dict(loc, grid=32),
         "roofline": {"bound": "mfma", "kernel": "k_mlp_grad (value + input gradient)",
                      "achieved": flops / (ms_mlp * 1e-3) / 1e12, "peak": MFMA_BF16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": flops / (ms_mlp * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,
@@ -513,6 +526,7 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
                                          "traffic_k_mlp_grad_4M.json", n),
                      "kernel_ms": ms_mlp},
     }
+    keep = keep_local
     if args.sur_oracle and not args.no_cpu_baseline:
         from oracle import oracle as O
         rng = np.random.default_rng(321)

@@ -260,6 +260,18 @@ int sd_surrogate_train_step(sd_surrogate *sur, const float *X, const float *labe
 int sd_surrogate_certify(sd_surrogate *sur, const float *X, const float *labels, int64_t n,
                          float safety, void *stream, float *eps_host);
 
+/* Local certificate: as sd_surrogate_certify (which it runs first, setting the
+ * global margin), plus a grid of grid^3 cells over the box [lo_host, hi_host]
+ * (host, 3 floats each): the margin of a cell is safety x the largest error of
+ * the held-out samples in the cell and its 26 neighbours (the global margin
+ * when there is none).  sd_eval_surrogate then routes a query inside the box
+ * when |y| < band + margin of its cell, outside the box with the global
+ * margin.  sd_surrogate_certify and sd_surrogate_load drop the grid.
+ * grid in [1, 256].  Synchronises `stream`. */
+int sd_surrogate_certify_cells(sd_surrogate *sur, const float *X, const float *labels, int64_t n,
+                               float safety, int grid, const float *lo_host, const float *hi_host,
+                               void *stream, float *eps_host);
+
 /* Host copies of the state (every output may be NULL): master parameters,
  * Adam moments (SD_SURR_N_PARAMS each), frequencies (64 x 3), step count,
  * certified margin.  Synchronous (device-wide). */
@@ -274,7 +286,8 @@ int sd_surrogate_load(sd_surrogate *sur, const float *theta_host, const float *m
 /* Smooth distance and gradient with the surrogate where it is certified:
  * every query gets the surrogate value y and gradient; the queries with
  * |y| < band + eps_cert (the certified margin of sd_surrogate_certify) are
- * then evaluated exactly (sd_eval_grad semantics with `params`, in Morton
+ * (or, after sd_surrogate_certify_cells, < band + the margin of the query's
+ * cell) are then evaluated exactly (sd_eval_grad semantics with `params`, in Morton
  * order unless SD_NO_QUERY_SORT) and overwritten.  routed (nQ bytes, may be
  * NULL) receives 1 for those queries.  *n_fallback_host (may be NULL) receives
  * their number.  The surrogate must have been trained for this scene and

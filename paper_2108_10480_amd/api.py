@@ -54,7 +54,7 @@ EXPORTED = ["sd_build_bvh", "sd_free_scene", "sd_scene_info_get", "sd_eval", "sd
             "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint",
             "sd_surrogate_create", "sd_surrogate_free", "sd_surrogate_forward",
             "sd_surrogate_loss_grad", "sd_surrogate_adam", "sd_surrogate_train_step",
-            "sd_surrogate_certify", "sd_surrogate_save", "sd_surrogate_load", "sd_eval_surrogate",
+            "sd_surrogate_certify", "sd_surrogate_certify_cells", "sd_surrogate_save", "sd_surrogate_load", "sd_eval_surrogate",
             "sd_last_error"]
 
 

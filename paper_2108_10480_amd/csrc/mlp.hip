@@ -163,7 +163,26 @@ struct MlpArgs {
     float band;            // routed[i] = |d_i| < band
     const float *label;    // certification: |d_i - label_i| -> err_out
     float *err_out;
+    // local certificate: routed[i] = |d_i| < band0 + eps of the query's cell
+    // (queries outside the grid box use band); cell_eps == nullptr: band only
+    const float *cell_eps;
+    float band0;
+    int grid;
+    float glo[3], ginv[3];
 };
+
+// cell of a point in the certificate grid, or -1 outside the grid box
+__device__ __forceinline__ int cert_cell(const MlpArgs &A, float x, float y, float z) {
+    float p[3] = {x, y, z};
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float t = (p[a] - A.glo[a]) * A.ginv[a];
+        if (!(t >= 0.f && t < (float)A.grid)) return -1;
+        c[a] = min((int)t, A.grid - 1);
+    }
+    return (c[0] * A.grid + c[1]) * A.grid + c[2];
+}
 
 // Weight stream through LDS: three 32 KB slots.  Chunk k is loaded straight
 // into slot k % 3 (global_load_lds, lane i -> slot base + 16 i) at the start
@@ -439,7 +458,14 @@ __device__ __forceinline__ void mlp_body(const MlpArgs &A, u32x4 *lds) {
                 A.g_out[3 * q + 1] = gx[qb][1];
                 A.g_out[3 * q + 2] = gx[qb][2];
             }
-            if (A.routed) A.routed[q] = fabsf(y[qb]) < A.band ? 1 : 0;
+            if (A.routed) {
+                float thr = A.band;
+                if (A.cell_eps) {
+                    int cell = cert_cell(A, x[qb][0], x[qb][1], x[qb][2]);
+                    if (cell >= 0) thr = A.band0 + A.cell_eps[cell];
+                }
+                A.routed[q] = fabsf(y[qb]) < thr ? 1 : 0;
+            }
             if (A.err_out) A.err_out[q] = fabsf(y[qb] - A.label[q]);
         }
     }
@@ -684,6 +710,40 @@ __global__ void k_compact(const uint8_t *__restrict__ f, const uint32_t *__restr
     if (i < n && f[i]) idx[pos[i]] = (uint32_t)i;
 }
 
+// per-cell maximum of the sample errors (non-negative floats order like their
+// bit patterns; -1 marks an empty cell)
+__global__ void k_cell_max(const float *__restrict__ X, const float *__restrict__ err, int64_t n,
+                           MlpArgs A, int *__restrict__ cell_bits) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    int c = cert_cell(A, X[3 * i], X[3 * i + 1], X[3 * i + 2]);
+    float e = err[i];
+    if (c >= 0) atomicMax(cell_bits + c, e == e ? __float_as_int(e) : 0x7f800000);
+}
+
+// certificate of a cell: safety x the largest error over the cell and its 26
+// neighbours; cells with no sample in that neighbourhood take eps_global
+__global__ void k_cell_final(const int *__restrict__ cell_bits, int G, float safety, float eps_global,
+                             float *__restrict__ cell_eps) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)G * G * G) return;
+    int cx = (int)(i / (G * G)), cy = (int)(i / G % G), cz = (int)(i % G);
+    int best = -1;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+                int x = cx + dx, y = cy + dy, z = cz + dz;
+                if (x < 0 || y < 0 || z < 0 || x >= G || y >= G || z >= G) continue;
+                best = max(best, cell_bits[((int64_t)x * G + y) * G + z]);
+            }
+    cell_eps[i] = best < 0 ? eps_global : safety * __int_as_float(best);
+}
+
+__global__ void k_fill_i32(int *__restrict__ p, int64_t n, int v) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -697,6 +757,11 @@ struct sd_surrogate {
     int64_t max_batch = 0;
     int64_t step = 0;
     float eps_cert = INFINITY;
+    // local certificate (grid^3 cells over [glo, ghi]); cell_eps null when absent
+    float *cell_eps = nullptr;
+    int64_t cell_cap = 0;
+    int grid = 0;
+    float glo[3] = {0.f, 0.f, 0.f}, ginv[3] = {0.f, 0.f, 0.f};
     float *Bf = nullptr;           // 64 x 3
     float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
     uint16_t *frag = nullptr;      // inference stream
@@ -736,7 +801,8 @@ int pack(sd_surrogate *h, hipStream_t s) {
 }
 
 int launch_mlp(const sd_surrogate *h, const float *Q, int64_t nq, float *d, float *gr,
-               uint8_t *routed, float band, const float *label, float *err, hipStream_t s) {
+               uint8_t *routed, float band, const float *label, float *err, hipStream_t s,
+               float band0 = 0.f) {
     if (nq <= 0) return SD_OK;
     MlpArgs A;
     A.frag = (const u32x4 *)h->frag;
@@ -752,6 +818,17 @@ int launch_mlp(const sd_surrogate *h, const float *Q, int64_t nq, float *d, floa
     A.band = band;
     A.label = label;
     A.err_out = err;
+    A.cell_eps = nullptr;
+    A.band0 = 0.f;
+    A.grid = h->grid;
+    for (int a = 0; a < 3; ++a) {
+        A.glo[a] = h->glo[a];
+        A.ginv[a] = h->ginv[a];
+    }
+    if (routed && h->grid > 0 && h->cell_eps) {
+        A.cell_eps = h->cell_eps;
+        A.band0 = band0;
+    }
     if (gr)
         hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)((nq + kGradQ - 1) / kGradQ)), dim3(64 * SD_MLP_GRAD_NW),
                            0, s, A);
@@ -910,6 +987,7 @@ extern "C" int sd_surrogate_create(const float *B_host, const float *theta_host,
 
 extern "C" int sd_surrogate_free(sd_surrogate *h) {
     if (!h) return SD_OK;
+    if (h->cell_eps) (void)hipFree(h->cell_eps);
     for (void *p : h->owned) (void)hipFree(p);
     delete h;
     return SD_OK;
@@ -981,7 +1059,51 @@ extern "C" int sd_surrogate_certify(sd_surrogate *h, const float *X, const float
     SD_HIP(hipFreeAsync(part, s));
     SD_HIP(hipStreamSynchronize(s));
     h->eps_cert = safety * mx;
+    h->grid = 0;   // a global certificate replaces any local one
     if (eps_host) *eps_host = h->eps_cert;
+    return SD_OK;
+}
+
+extern "C" int sd_surrogate_certify_cells(sd_surrogate *h, const float *X, const float *y, int64_t n,
+                                          float safety, int grid, const float *lo_host,
+                                          const float *hi_host, void *stream, float *eps_host) {
+    if (!h || !lo_host || !hi_host) return fail(SD_EINVAL, "sd_surrogate_certify_cells: null argument");
+    if (grid < 1 || grid > 256) return fail(SD_EINVAL, "sd_surrogate_certify_cells: grid must be in [1, 256]");
+    for (int a = 0; a < 3; ++a)
+        if (!(hi_host[a] > lo_host[a])) return fail(SD_EINVAL, "sd_surrogate_certify_cells: empty box");
+    SD_TRY(sd_surrogate_certify(h, X, y, n, safety, stream, eps_host));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nc = (int64_t)grid * grid * grid;
+    if (h->cell_eps && h->cell_cap < nc) {
+        SD_HIP(hipFree(h->cell_eps));
+        h->cell_eps = nullptr;
+    }
+    if (!h->cell_eps) {
+        SD_HIP(hipMalloc((void **)&h->cell_eps, nc * sizeof(float)));
+        h->cell_cap = nc;
+    }
+    MlpArgs A = {};
+    A.grid = grid;
+    for (int a = 0; a < 3; ++a) {
+        h->glo[a] = lo_host[a];
+        h->ginv[a] = (float)grid / (hi_host[a] - lo_host[a]);
+        A.glo[a] = h->glo[a];
+        A.ginv[a] = h->ginv[a];
+    }
+    float *err = nullptr;
+    int *bits = nullptr;
+    SD_HIP(hipMallocAsync((void **)&err, n * sizeof(float), s));
+    SD_HIP(hipMallocAsync((void **)&bits, nc * sizeof(int), s));
+    SD_TRY(launch_mlp(h, X, n, nullptr, nullptr, nullptr, 0.f, y, err, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nc)), dim3(256), 0, s, bits, nc, -1);
+    hipLaunchKernelGGL(k_cell_max, dim3(blocks(n)), dim3(256), 0, s, X, err, n, A, bits);
+    hipLaunchKernelGGL(k_cell_final, dim3(blocks(nc)), dim3(256), 0, s, bits, grid, safety, h->eps_cert,
+                       h->cell_eps);
+    SD_HIP(hipGetLastError());
+    SD_HIP(hipFreeAsync(err, s));
+    SD_HIP(hipFreeAsync(bits, s));
+    SD_HIP(hipStreamSynchronize(s));
+    h->grid = grid;
     return SD_OK;
 }
 
@@ -1009,6 +1131,7 @@ extern "C" int sd_surrogate_load(sd_surrogate *h, const float *theta_host, const
     else SD_HIP(hipMemsetAsync(h->v, 0, NPAR * sizeof(float), s));
     h->step = step;
     h->eps_cert = eps_cert;
+    h->grid = 0;
     return pack(h, s);
 }
 
@@ -1030,7 +1153,7 @@ extern "C" int sd_eval_surrogate(const sd_scene *sc, const sd_surrogate *h, cons
     uint32_t *f32 = nullptr, *pos = nullptr, *idx = nullptr, *ord = nullptr;
     void *temp = nullptr;
     if (!flag) SD_HIP(hipMallocAsync((void **)&flag, nQ, s));
-    SD_TRY(launch_mlp(h, Q, nQ, d_out, grad_out, flag, band + h->eps_cert, nullptr, nullptr, s));
+    SD_TRY(launch_mlp(h, Q, nQ, d_out, grad_out, flag, band + h->eps_cert, nullptr, nullptr, s, band));
     // compaction of the routed queries (in index order), then Morton order
     SD_HIP(hipMallocAsync((void **)&f32, nQ * sizeof(uint32_t), s));
     SD_HIP(hipMallocAsync((void **)&pos, nQ * sizeof(uint32_t), s));

@@ -95,6 +95,18 @@ class Surrogate:
                                           _stream(), ctypes.byref(eps)))
         return eps.value
 
+    def certify_cells(self, X, labels, lo, hi, grid=32, safety=1.5):
+        """Global margin (returned) plus a grid of local margins over [lo, hi]."""
+        Xp, n = _dptr(X, torch.float32, "X", 3)
+        yp, _ = _dptr(labels, torch.float32, "labels")
+        lo = np.ascontiguousarray(lo, np.float32)
+        hi = np.ascontiguousarray(hi, np.float32)
+        eps = ctypes.c_float()
+        _check(lib().sd_surrogate_certify_cells(self.handle, Xp, yp, _i64(n), ctypes.c_float(safety),
+                                                ctypes.c_int(grid), _c_p(lo.ctypes.data), _c_p(hi.ctypes.data),
+                                                _stream(), ctypes.byref(eps)))
+        return eps.value
+
     def save(self):
         th, m, v = (np.empty(N_PARAMS, np.float32) for _ in range(3))
         B = np.empty((N_FREQ, 3), np.float32)

@@ -215,3 +215,56 @@ def test_routing_to_exact_evaluation(nq, flags):
     sur.load(th, eps_cert=float("inf"))
     d1, _, r1, n1 = S.sd_eval_surrogate(scene, sur, Xd, 50.0, 0.5, band=0.05)
     assert n1 == nq and bool(r1.all())
+
+
+def _cells(X, lo, ginv, G):
+    """Certificate cell of each point (same FP32 operations as the library), -1 outside."""
+    t = (X.astype(np.float32) - lo.astype(np.float32)) * ginv
+    inside = np.all((t >= 0) & (t < np.float32(G)), axis=1)
+    c = np.minimum(np.floor(np.where(inside[:, None], t, 0)).astype(np.int64), G - 1)
+    return np.where(inside, (c[:, 0] * G + c[:, 1]) * G + c[:, 2], -1)
+
+
+def test_local_certificate_and_routing():
+    require_gpu()
+    from paper_2108_10480_amd import surrogate as S
+    sc = scenes.bumpy_icosphere(level=3, seed=16)
+    scene = api.upload_scene(sc)
+    sur, th, B = _surrogate(seed=19, scale=2.0)
+    rng = np.random.default_rng(20)
+    Xv = rng.uniform(-1.5, 1.5, (20000, 3)).astype(np.float32)
+    # held-out labels that disagree with the network by a small amount for
+    # x < 0 and a large one for x > 0, so that the local margins differ
+    y0 = sur.forward(cuda(Xv), grad=False).cpu().numpy()
+    amp = np.where(Xv[:, 0] < 0, 1e-3, 0.3).astype(np.float32)
+    lab = (y0 + amp * rng.standard_normal(len(Xv)).astype(np.float32)).astype(np.float32)
+    G, safety = 8, 1.5
+    lo = np.full(3, -1.5, np.float32)
+    hi = np.full(3, 1.5, np.float32)
+    eps = sur.certify_cells(cuda(Xv), cuda(lab), lo, hi, grid=G, safety=safety)
+    y = sur.forward(cuda(Xv), grad=False).cpu().numpy()
+    err = np.abs(y - lab)
+    assert eps == np.float32(safety) * err.max()
+    ginv = (np.float32(G) / (hi - lo)).astype(np.float32)
+    cell = _cells(Xv, lo, ginv, G)
+    cmax = np.full(G ** 3, -1.0, np.float32)
+    np.maximum.at(cmax, cell[cell >= 0], err[cell >= 0])
+    cm = cmax.reshape(G, G, G)
+    pad = np.pad(cm, 1, constant_values=-1.0)
+    nb = np.max([pad[1 + a:1 + a + G, 1 + b:1 + b + G, 1 + c:1 + c + G]
+                 for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)], axis=0).reshape(-1)
+    ceps = np.where(nb < 0, np.float32(eps), np.float32(safety) * nb).astype(np.float32)
+    # routing with the local margins (queries partly outside the grid box)
+    Xq = rng.uniform(-1.7, 1.7, (30000, 3)).astype(np.float32)
+    yq = sur.forward(cuda(Xq), grad=False).cpu().numpy()
+    band = np.float32(0.05)
+    d, g, routed, nfb = S.sd_eval_surrogate(scene, sur, cuda(Xq), 50.0, 0.5, band=float(band))
+    cq = _cells(Xq, lo, ginv, G)
+    thr = np.where(cq >= 0, band + ceps[np.maximum(cq, 0)], band + np.float32(eps)).astype(np.float32)
+    want = np.abs(yq) < thr
+    assert np.array_equal(routed.cpu().numpy().astype(bool), want)
+    assert nfb == int(want.sum()) and 0 < nfb < len(Xq)
+    # a global certificate drops the grid
+    eps2 = sur.certify(cuda(Xv), cuda(lab), safety=safety)
+    _, _, r2, n2 = S.sd_eval_surrogate(scene, sur, cuda(Xq), 50.0, 0.5, band=float(band))
+    assert np.array_equal(r2.cpu().numpy().astype(bool), np.abs(yq) < band + np.float32(eps2))
