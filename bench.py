@@ -78,9 +78,10 @@ def main():
     ap.add_argument("--sweep-scale", type=float, default=0.1,
                     help="size of the sweep scene relative to 20M points, 1M triangles, 200k edges, 32M queries")
     ap.add_argument("--sur-train", type=int, default=20_000_000, help="surrogate training samples")
-    ap.add_argument("--sur-epochs", type=int, default=40)
+    ap.add_argument("--sur-epochs", type=int, default=80)
     ap.add_argument("--sur-nq", type=int, default=16_000_000, help="surrogate inference queries")
     ap.add_argument("--sur-oracle", type=int, default=20000, help="oracle-checked queries of the surrogate path")
+    ap.add_argument("--sur-grid", type=int, default=32, help="cells per axis of the local certificate")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 3 plain device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -498,7 +499,8 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
 
     # global certificate (one margin everywhere), then a local one (32^3 cells)
     ms_sur, nfb, keep, glob = routed_run()
-    eps_local = sur.certify_cells(Xva, yva, lo=(-1.5, -1.5, -1.5), hi=(1.5, 1.5, 1.5), grid=32, safety=1.5)
+    eps_local = sur.certify_cells(Xva, yva, lo=(-1.5, -1.5, -1.5), hi=(1.5, 1.5, 1.5), grid=args.sur_grid,
+                                  safety=1.5)
     _, _, keep_local, loc = routed_run()
     flops = n * 2.0 * (SUR_FWD_MACS + SUR_BWD_MACS)
     res = {
@@ -517,7 +519,7 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
         "value_barnes_hut": n / (ms_bh * 1e-3),
         "ms": {"barnes_hut": ms_bh, "mlp_value_grad": ms_mlp},
         "global_certificate": glob,
-        "local_certificate": dict(loc, grid=32),
+        "local_certificate": dict(loc, grid=args.sur_grid),
         "roofline": {"bound": "mfma", "kernel": "k_mlp_grad (value + input gradient)",
                      "achieved": flops / (ms_mlp * 1e-3) / 1e12, "peak": MFMA_BF16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": flops / (ms_mlp * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,

@@ -597,8 +597,16 @@ __device__ __forceinline__ void lse_init(LSE &st) {
     st.gx = st.gy = st.gz = st.cx = st.cy = st.cz = 0.f;
 }
 
+// Waves per SIMD the traversal is compiled for (register budget); the
+// default lets the compiler choose (about 115 registers, 4 waves).
+#ifdef SD_EVAL_WPE
+#define SD_EVAL_ATTR __attribute__((amdgpu_waves_per_eu(SD_EVAL_WPE, SD_EVAL_WPE)))
+#else
+#define SD_EVAL_ATTR
+#endif
+
 template <bool GRAD, bool COUNT, int MASK>
-__global__ void __launch_bounds__(kB) k_eval(EvalArgs A) {
+__global__ void __launch_bounds__(kB) SD_EVAL_ATTR k_eval(EvalArgs A) {
     int i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
     if (i >= A.nthr) return;
     int qi = A.perm ? (int)A.perm[i] : i;
