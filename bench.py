@@ -27,13 +27,13 @@ HBM_PEAK_GBS = 8000.0
 # disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 78.6
 ALU_PEAK_PACKED_TFLOPS = 157.3
-# algorithmic FLOPs per unit of work, value + gradient (see the design notes):
+# algorithmic FLOPs per unit of work, value + gradient, counted from the kernel's arithmetic:
 F_QUERY = 50        # load, seed bookkeeping, finalisation
 F_NODE = 26         # box distance, box diagonal, opening and pruning tests
 F_FAR = 35          # sqrt, rcp, direction, exponent, compensated sums
 F_TRI_LEAF = 636    # distance + region, de Casteljau weight, gradient, sums
 METRIC = "smooth-distance+grad queries/s on 1 MI355X: BH vs surrogate at ≤1e-5 rel / 1e-3 abs"
-# algorithmic bytes per unit of work (see the design notes)
+# algorithmic bytes per unit of work: query in, outputs out, node and leaf records read
 B_QUERY = 12 + 16 + 4        # query in, value + gradient out, order index
 B_NODE = 32                  # one hierarchy node record
 B_TRI_LEAF = 48              # one triangle leaf record
@@ -95,8 +95,9 @@ def main():
         print(json.dumps({"copy_bytes": x.numel() * 4}))
         return
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
-              "(queries shard with no communication; see the design notes)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported; the library runs on one GPU "
+              "(queries are independent: several GPUs would each take a share of them against a "
+              "replicated scene)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -16,7 +16,7 @@ What lives here (each function cites the passage it follows):
 * the surrogate network in FP64 (forward, backward, input gradient, Adam):
   see ``mlp.py``
 
-Readings of ambiguous passages (each also listed in the design notes):
+Readings of ambiguous passages:
 * App. C.2's derivative constraints are read as w'(0) = w'(1) = 0.
 * App. C.3's "A = max_i v_i" is strengthened to A_T = max(max_i v_i,
   max_i 1/min w~_i) so that A w~_i >= 1 holds everywhere as Sec. 3.3 requires
