@@ -503,6 +503,12 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
     eps_local = sur.certify_cells(Xva, yva, lo=(-1.5, -1.5, -1.5), hi=(1.5, 1.5, 1.5), grid=args.sur_grid,
                                   safety=1.5)
     _, _, keep_local, loc = routed_run()
+    # the same local certificate with the 1e-3 target enforced by routing
+    sur.certify_cells(Xva, yva, lo=(-1.5, -1.5, -1.5), hi=(1.5, 1.5, 1.5), grid=args.sur_grid, safety=1.5,
+                      max_margin=1e-3)
+    _, _, _, gate = routed_run()
+    sur.certify_cells(Xva, yva, lo=(-1.5, -1.5, -1.5), hi=(1.5, 1.5, 1.5), grid=args.sur_grid, safety=1.5)
+    routed_run()
     flops = n * 2.0 * (SUR_FWD_MACS + SUR_BWD_MACS)
     res = {
         "workload": f"same scene, {n} queries uniform in [-1.5,1.5]^3, alpha={alpha:g}, beta={beta:g}, "
@@ -521,6 +527,7 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
         "ms": {"barnes_hut": ms_bh, "mlp_value_grad": ms_mlp},
         "global_certificate": glob,
         "local_certificate": dict(loc, grid=args.sur_grid),
+        "local_certificate_1e-3_target": dict(gate, grid=args.sur_grid, max_margin=1e-3),
         "roofline": {"bound": "mfma", "kernel": "k_mlp_grad (value + input gradient)",
                      "achieved": flops / (ms_mlp * 1e-3) / 1e12, "peak": MFMA_BF16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": flops / (ms_mlp * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,

@@ -266,11 +266,14 @@ int sd_surrogate_certify(sd_surrogate *sur, const float *X, const float *labels,
  * the held-out samples in the cell and its 26 neighbours (the global margin
  * when there is none).  sd_eval_surrogate then routes a query inside the box
  * when |y| < band + margin of its cell, outside the box with the global
- * margin.  sd_surrogate_certify and sd_surrogate_load drop the grid.
- * grid in [1, 256].  Synchronises `stream`. */
+ * margin.  A cell whose margin exceeds max_margin (> 0; +inf for no limit)
+ * sends every query in it to the exact evaluation, so that the error of the
+ * answers left to the network stays within max_margin (empirically).
+ * sd_surrogate_certify and sd_surrogate_load drop the grid.  grid in
+ * [1, 256].  Synchronises `stream`. */
 int sd_surrogate_certify_cells(sd_surrogate *sur, const float *X, const float *labels, int64_t n,
                                float safety, int grid, const float *lo_host, const float *hi_host,
-                               void *stream, float *eps_host);
+                               float max_margin, void *stream, float *eps_host);
 
 /* Host copies of the state (every output may be NULL): master parameters,
  * Adam moments (SD_SURR_N_PARAMS each), frequencies (64 x 3), step count,

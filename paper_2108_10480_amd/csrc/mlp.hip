@@ -171,14 +171,14 @@ struct MlpArgs {
     float glo[3], ginv[3];
 };
 
-// cell of a point in the certificate grid, or -1 outside the grid box
+// cell of a point in the certificate grid, or -1 outside the (closed) grid box
 __device__ __forceinline__ int cert_cell(const MlpArgs &A, float x, float y, float z) {
     float p[3] = {x, y, z};
     int c[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float t = (p[a] - A.glo[a]) * A.ginv[a];
-        if (!(t >= 0.f && t < (float)A.grid)) return -1;
+        if (!(t >= 0.f && t <= (float)A.grid)) return -1;
         c[a] = min((int)t, A.grid - 1);
     }
     return (c[0] * A.grid + c[1]) * A.grid + c[2];
@@ -724,7 +724,7 @@ __global__ void k_cell_max(const float *__restrict__ X, const float *__restrict_
 // certificate of a cell: safety x the largest error over the cell and its 26
 // neighbours; cells with no sample in that neighbourhood take eps_global
 __global__ void k_cell_final(const int *__restrict__ cell_bits, int G, float safety, float eps_global,
-                             float *__restrict__ cell_eps) {
+                             float max_margin, float *__restrict__ cell_eps) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= (int64_t)G * G * G) return;
     int cx = (int)(i / (G * G)), cy = (int)(i / G % G), cz = (int)(i % G);
@@ -736,7 +736,8 @@ __global__ void k_cell_final(const int *__restrict__ cell_bits, int G, float saf
                 if (x < 0 || y < 0 || z < 0 || x >= G || y >= G || z >= G) continue;
                 best = max(best, cell_bits[((int64_t)x * G + y) * G + z]);
             }
-    cell_eps[i] = best < 0 ? eps_global : safety * __int_as_float(best);
+    float e = best < 0 ? eps_global : safety * __int_as_float(best);
+    cell_eps[i] = e > max_margin ? INFINITY : e;   // cells above the target route every query
 }
 
 __global__ void k_fill_i32(int *__restrict__ p, int64_t n, int v) {
@@ -1066,7 +1067,9 @@ extern "C" int sd_surrogate_certify(sd_surrogate *h, const float *X, const float
 
 extern "C" int sd_surrogate_certify_cells(sd_surrogate *h, const float *X, const float *y, int64_t n,
                                           float safety, int grid, const float *lo_host,
-                                          const float *hi_host, void *stream, float *eps_host) {
+                                          const float *hi_host, float max_margin, void *stream,
+                                          float *eps_host) {
+    if (!(max_margin > 0.f)) return fail(SD_EINVAL, "sd_surrogate_certify_cells: max_margin must be > 0");
     if (!h || !lo_host || !hi_host) return fail(SD_EINVAL, "sd_surrogate_certify_cells: null argument");
     if (grid < 1 || grid > 256) return fail(SD_EINVAL, "sd_surrogate_certify_cells: grid must be in [1, 256]");
     for (int a = 0; a < 3; ++a)
@@ -1098,7 +1101,7 @@ extern "C" int sd_surrogate_certify_cells(sd_surrogate *h, const float *X, const
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nc)), dim3(256), 0, s, bits, nc, -1);
     hipLaunchKernelGGL(k_cell_max, dim3(blocks(n)), dim3(256), 0, s, X, err, n, A, bits);
     hipLaunchKernelGGL(k_cell_final, dim3(blocks(nc)), dim3(256), 0, s, bits, grid, safety, h->eps_cert,
-                       h->cell_eps);
+                       max_margin, h->cell_eps);
     SD_HIP(hipGetLastError());
     SD_HIP(hipFreeAsync(err, s));
     SD_HIP(hipFreeAsync(bits, s));

@@ -95,8 +95,9 @@ class Surrogate:
                                           _stream(), ctypes.byref(eps)))
         return eps.value
 
-    def certify_cells(self, X, labels, lo, hi, grid=32, safety=1.5):
-        """Global margin (returned) plus a grid of local margins over [lo, hi]."""
+    def certify_cells(self, X, labels, lo, hi, grid=32, safety=1.5, max_margin=math.inf):
+        """Global margin (returned) plus a grid of local margins over [lo, hi];
+        cells whose margin exceeds max_margin route every query."""
         Xp, n = _dptr(X, torch.float32, "X", 3)
         yp, _ = _dptr(labels, torch.float32, "labels")
         lo = np.ascontiguousarray(lo, np.float32)
@@ -104,7 +105,7 @@ class Surrogate:
         eps = ctypes.c_float()
         _check(lib().sd_surrogate_certify_cells(self.handle, Xp, yp, _i64(n), ctypes.c_float(safety),
                                                 ctypes.c_int(grid), _c_p(lo.ctypes.data), _c_p(hi.ctypes.data),
-                                                _stream(), ctypes.byref(eps)))
+                                                ctypes.c_float(max_margin), _stream(), ctypes.byref(eps)))
         return eps.value
 
     def save(self):

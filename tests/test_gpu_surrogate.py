@@ -220,7 +220,7 @@ def test_routing_to_exact_evaluation(nq, flags):
 def _cells(X, lo, ginv, G):
     """Certificate cell of each point (same FP32 operations as the library), -1 outside."""
     t = (X.astype(np.float32) - lo.astype(np.float32)) * ginv
-    inside = np.all((t >= 0) & (t < np.float32(G)), axis=1)
+    inside = np.all((t >= 0) & (t <= np.float32(G)), axis=1)
     c = np.minimum(np.floor(np.where(inside[:, None], t, 0)).astype(np.int64), G - 1)
     return np.where(inside, (c[:, 0] * G + c[:, 1]) * G + c[:, 2], -1)
 
@@ -264,6 +264,16 @@ def test_local_certificate_and_routing():
     want = np.abs(yq) < thr
     assert np.array_equal(routed.cpu().numpy().astype(bool), want)
     assert nfb == int(want.sum()) and 0 < nfb < len(Xq)
+    # a margin cap: cells above it route every query (the cap splits the
+    # cells of the accurate half)
+    cap = np.float32(np.median(ceps[ceps < 0.1]))
+    sur.certify_cells(cuda(Xv), cuda(lab), lo, hi, grid=G, safety=safety, max_margin=float(cap))
+    _, _, rc, nc = S.sd_eval_surrogate(scene, sur, cuda(Xq), 50.0, 0.5, band=float(band))
+    ceps_c = np.where(ceps > cap, np.float32(np.inf), ceps)
+    thr_c = np.where(cq >= 0, band + ceps_c[np.maximum(cq, 0)], band + np.float32(eps)).astype(np.float32)
+    want_c = np.abs(yq) < thr_c
+    assert np.array_equal(rc.cpu().numpy().astype(bool), want_c)
+    assert nc == int(want_c.sum()) and nc > nfb
     # a global certificate drops the grid
     eps2 = sur.certify(cuda(Xv), cuda(lab), safety=safety)
     _, _, r2, n2 = S.sd_eval_surrogate(scene, sur, cuda(Xq), 50.0, 0.5, band=float(band))
