@@ -444,7 +444,11 @@ __device__ __forceinline__ float seed_distance(const TreeView &T, float qx, floa
 
 // Per-wave LDS queue of the cooperative leaf stage: queued leaf slots and their
 // results, lane-minor so that the 64 lanes touch consecutive banks.
-constexpr int kQ = 4;
+#ifndef SD_LEAF_QUEUE
+#define SD_LEAF_QUEUE 5
+#endif
+constexpr int kQ = SD_LEAF_QUEUE;   // queued leaves per lane
+static_assert(kQ >= 1 && kQ <= 7, "leaf queue depth (three bits in an entry and in the count)");
 struct LeafQueue {
     int slot[kQ][64];
     int ent[kQ * 64];
@@ -506,7 +510,7 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
             }
         }
         if (__ballot(cnt > 0) == 0) break;
-        // exclusive prefix of the per-lane counts (kQ <= 4: two bit planes)
+        // exclusive prefix of the per-lane counts (kQ <= 7: three bit planes)
         int off = 0, total = 0;
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
@@ -514,7 +518,7 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
             total += __popcll(m) << b;
             off += __popcll(m & lt) << b;
         }
-        for (int k = 0; k < cnt; ++k) lq.ent[off + k] = (lane << 2) | k;
+        for (int k = 0; k < cnt; ++k) lq.ent[off + k] = (lane << 3) | k;
         wave_sync();
         // spread the entries over the lanes still present in the wave (lanes
         // past the end of the query array have already exited)
@@ -524,7 +528,7 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
             int e = base + rank;
             bool act = e < total;
             int code = act ? lq.ent[e] : 0;
-            int owner = code >> 2, k = code & 3;
+            int owner = code >> 3, k = code & 7;
             float ox = __shfl(qx, owner, 64), oy = __shfl(qy, owner, 64), oz = __shfl(qz, owner, 64);
             if (act) {
                 Term t = leaf_term<CLS, GRAD>(T, A, lq.slot[k][owner], leaf_lo, ox, oy, oz, metric);
