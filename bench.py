@@ -68,7 +68,8 @@ def main():
     ap.add_argument("--beta", type=float, default=0.5)
     ap.add_argument("--level", type=int, default=7)
     ap.add_argument("--nq", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=250000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="queries of the workload timed on the FP64 oracle (0: all of them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate comparison")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid-body street workload")
@@ -233,7 +234,8 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         rng = np.random.default_rng(123)
-        idx = np.sort(rng.choice(n, size=min(args.cpu_sample, n), replace=False))
+        k = n if args.cpu_sample <= 0 else min(args.cpu_sample, n)
+        idx = np.sort(rng.choice(n, size=k, replace=False)) if k < n else np.arange(n)
         trees = [None, None, O.OracleTree(*api.sd_export_bvh(scene, 2))]
         osc = O.OracleScene(sc.V, T=sc.T)
         Qs = Q[idx].astype(np.float64)
@@ -247,8 +249,8 @@ def main():
         err = O.value_error(d_s, dr, dm_floor)[ok]
         out["cpu_baseline"] = {
             "value": len(idx) / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(idx)} random queries of the same workload, FP64 Barnes-Hut oracle "
-                      f"on the exported hierarchy ({dt:.1f} s)",
+            "sample": f"{len(idx)} queries of the same workload ({'all' if len(idx) == n else 'random'}), "
+                      f"FP64 Barnes-Hut oracle on the exported hierarchy ({dt:.1f} s)",
         }
         out["parity_sample"] = {"max_err_vs_oracle": float(err.max()),
                                 "metric": "|d - d_oracle| / max(|d_oracle|, 1e-3 scene diagonal); d includes "
