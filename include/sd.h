@@ -56,7 +56,8 @@ enum {
 #define SD_NO_CONSERVATIVE_ROUNDING 0x8u /* skip the downward rounding of terms and result     */
 #define SD_NO_PRUNE          0x10u  /* visit every node Alg. 1 visits, even subtrees whose terms
                                        are all below exp(-64) of the running maximum (by default
-                                       those are skipped: they cannot change an FP32 result)   */
+                                       those are skipped when alpha x scene diagonal > 1000:
+                                       they cannot change an FP32 result)                      */
 
 typedef struct sd_params {
     float alpha;     /* accuracy / smoothness, > 0 (Eq. 3)                                   */

@@ -347,13 +347,13 @@ __device__ __forceinline__ Term leaf_term(const TreeView &T, const EvalArgs &A, 
 
 // One node of Alg. 1: the opening test, then the far-field term (App. D) or a
 // leaf hand-off or descent.  Returns the leaf slot to evaluate, or -1.
-template <bool GRAD, bool COUNT>
+template <bool GRAD, bool COUNT, bool PRUNE>
 __device__ __forceinline__ int node_step(const TreeView &T, const EvalArgs &A, float qx, float qy,
                                          float qz, LSE &st, int &node, float4 &leaf_lo, int &n_vis,
                                          int &n_far);
 
 // node_step on a node whose record (lo, hi) is already in registers
-template <bool GRAD, bool COUNT>
+template <bool GRAD, bool COUNT, bool PRUNE>
 __device__ __forceinline__ int node_test(const TreeView &T, const EvalArgs &A, float qx, float qy,
                                          float qz, LSE &st, float4 lo, float4 hi, int &node,
                                          float4 &leaf_lo, int &n_vis, int &n_far) {
@@ -374,10 +374,12 @@ __device__ __forceinline__ int node_test(const TreeView &T, const EvalArgs &A, f
     // the running reference is below -A.prune (64: < 1e-27 of the sum), so it
     // cannot change the FP32 result; skip it.  D > d* + (log n_B + log W_max
     // - l* + prune)/alpha, tested on squares.
-    float thr = fmaf(logn + T.lwmax - st.lref + A.prune, A.inv_alpha, st.dref);
-    if (thr < 0.f || D2 > thr * thr) {
-        node = esc;
-        return -1;
+    if (PRUNE) {
+        float thr = fmaf(logn + T.lwmax - st.lref + A.prune, A.inv_alpha, st.dref);
+        if (thr < 0.f || D2 > thr * thr) {
+            node = esc;
+            return -1;
+        }
     }
     if (diag2 < A.beta2 * D2) {
         // far field at the closest box point y_B: weight n_B A^S (App. D)
@@ -397,11 +399,11 @@ __device__ __forceinline__ int node_test(const TreeView &T, const EvalArgs &A, f
     return slot;
 }
 
-template <bool GRAD, bool COUNT>
+template <bool GRAD, bool COUNT, bool PRUNE>
 __device__ __forceinline__ int node_step(const TreeView &T, const EvalArgs &A, float qx, float qy,
                                          float qz, LSE &st, int &node, float4 &leaf_lo, int &n_vis,
                                          int &n_far) {
-    return node_test<GRAD, COUNT>(T, A, qx, qy, qz, st, T.lo[2 * node], T.hi[2 * node], node, leaf_lo,
+    return node_test<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, T.lo[2 * node], T.hi[2 * node], node, leaf_lo,
                                   n_vis, n_far);
 }
 
@@ -462,7 +464,7 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int CLS, bool GRAD, bool COUNT>
+template <int CLS, bool GRAD, bool COUNT, bool PRUNE>
 __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, float qx, float qy,
                                          float qz, LSE &st, int &n_vis, int &n_far, int &n_leaf,
                                          LeafQueue &lq) {
@@ -478,7 +480,7 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
     }
     if (CLS == 0 || A.defer == 0) {
         while (node >= 0) {
-            int slot = node_step<GRAD, COUNT>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
+            int slot = node_step<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
             if (slot >= 0) {
                 if (COUNT) ++n_leaf;
                 Term t = leaf_term<CLS, GRAD>(T, A, slot, leaf_lo, qx, qy, qz, metric);
@@ -501,7 +503,7 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
             if (__ballot(can) == 0) break;
             if (__ballot(node >= 0 && cnt >= kQ)) break;   // flush before a lane stalls
             if (can) {
-                int slot = node_step<GRAD, COUNT>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
+                int slot = node_step<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
                 if (slot >= 0) {
                     lq.slot[cnt][lane] = slot;
                     ++cnt;
@@ -621,9 +623,10 @@ __global__ void __launch_bounds__(kB) SD_EVAL_ATTR k_eval(EvalArgs A) {
     LSE st;
     lse_init(st);
     int nv = 0, nf = 0, nl = 0;
-    if (MASK & 1) traverse<0, GRAD, COUNT>(A.tree[0], A, qx, qy, qz, st, nv, nf, nl, lq);
-    if (MASK & 2) traverse<1, GRAD, COUNT>(A.tree[1], A, qx, qy, qz, st, nv, nf, nl, lq);
-    if (MASK & 4) traverse<2, GRAD, COUNT>(A.tree[2], A, qx, qy, qz, st, nv, nf, nl, lq);
+    constexpr bool PRUNE = (MASK & 8) != 0;
+    if (MASK & 1) traverse<0, GRAD, COUNT, PRUNE>(A.tree[0], A, qx, qy, qz, st, nv, nf, nl, lq);
+    if (MASK & 2) traverse<1, GRAD, COUNT, PRUNE>(A.tree[1], A, qx, qy, qz, st, nv, nf, nl, lq);
+    if (MASK & 4) traverse<2, GRAD, COUNT, PRUNE>(A.tree[2], A, qx, qy, qz, st, nv, nf, nl, lq);
     if (COUNT) {
         A.counts[3 * (int64_t)qi] = nv;
         A.counts[3 * (int64_t)qi + 1] = nf;
@@ -708,6 +711,7 @@ void launch_eval(const EvalArgs &A, int mask, unsigned grid, hipStream_t s) {
 #define SD_CASE(m) \
     case m: hipLaunchKernelGGL((k_eval<GRAD, COUNT, m>), dim3(grid), dim3(kB), 0, s, A); break;
         SD_CASE(1) SD_CASE(2) SD_CASE(3) SD_CASE(4) SD_CASE(5) SD_CASE(6) SD_CASE(7)
+        SD_CASE(9) SD_CASE(10) SD_CASE(11) SD_CASE(12) SD_CASE(13) SD_CASE(14) SD_CASE(15)
 #undef SD_CASE
         default: break;
     }
@@ -790,7 +794,7 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
     A.margin_scale = ldexpf(1.f, -22);
     A.cons = (p->flags & SD_NO_CONSERVATIVE_ROUNDING) ? 0.f : 1.f;
     A.defer = defer_threshold();
-    A.prune = (p->flags & SD_NO_PRUNE) ? INFINITY : 64.f;
+    A.prune = 64.f;
     A.flags = p->flags;
     A.nq = (int32_t)nq;
     A.nthr = (int32_t)nthr;
@@ -800,6 +804,15 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
     A.counts = counts;
     int mask = (sc->n[0] > 0 ? 1 : 0) | (sc->n[1] > 0 ? 2 : 0) | (sc->n[2] > 0 ? 4 : 0);
     unsigned grid = (unsigned)((nthr + kB - 1) / kB);
+    // Negligible-subtree skipping (bit 8 of the kernel variant) only where it
+    // can pay for its per-node test: a subtree is skipped when it lies at
+    // least 64/alpha beyond the running reference, which inside a scene of
+    // diagonal L happens only for alpha L well above 64.
+    {
+        double ex = sc->box[3] - sc->box[0], ey = sc->box[4] - sc->box[1], ez = sc->box[5] - sc->box[2];
+        double diag = sqrt(ex * ex + ey * ey + ez * ez);
+        if (mask != 0 && !(p->flags & SD_NO_PRUNE) && alpha * diag > 1000.0) mask |= 8;
+    }
 
     if (mask == 0) {
         // empty scene: the empty sum gives +inf and a zero gradient
