@@ -74,7 +74,7 @@ class _OrScene(ctypes.Structure):
 class _OrParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("alpha_u", ctypes.c_double),
                 ("beta", ctypes.c_double), ("metric_r2", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("cut_f32", ctypes.c_int32)]
 
 
 class _OrTree(ctypes.Structure):
@@ -319,9 +319,9 @@ class OracleScene:
         return s
 
 
-def _params(alpha, alpha_u=0.0, beta=0.0, metric_r2=False):
+def _params(alpha, alpha_u=0.0, beta=0.0, metric_r2=False, cut_f32=False):
     p = _OrParams()
-    p.alpha, p.alpha_u, p.beta, p.metric_r2, p.pad = alpha, alpha_u, beta, int(metric_r2), 0
+    p.alpha, p.alpha_u, p.beta, p.metric_r2, p.cut_f32 = alpha, alpha_u, beta, int(metric_r2), int(cut_f32)
     return p
 
 
@@ -375,12 +375,17 @@ class OracleTree:
         return t
 
 
-def barnes_hut(scene: OracleScene, trees, Q, alpha, beta, alpha_u=0.0, metric_r2=False):
+def barnes_hut(scene: OracleScene, trees, Q, alpha, beta, alpha_u=0.0, metric_r2=False, cut_f32=False):
     """Alg. 1 + Alg. 2 with the conservative far field of App. D on given
     hierarchies (``trees`` = [points, edges, triangles], None for an empty
     class).  Returns (d, grad, stats) with stats[:, 0] the smallest relative
     opening-criterion margin |beta D - |B|| / D met by each query and
-    stats[:, 1:4] = nodes visited, far-field terms, exact leaves."""
+    stats[:, 1:4] = nodes visited, far-field terms, exact leaves.
+
+    ``cut_f32``: take the open/accept decision |B| < beta D (Sec. 3.5) in
+    FP32 on squared lengths, as a single-precision evaluator takes it, so that
+    both pick the same terms; the terms themselves stay FP64.  Queries should
+    then be FP32 values (they are rounded to FP32 for the decision)."""
     Q = np.ascontiguousarray(Q, np.float64)
     n = len(Q)
     arr = (_OrTree * 3)()
@@ -390,7 +395,7 @@ def barnes_hut(scene: OracleScene, trees, Q, alpha, beta, alpha_u=0.0, metric_r2
         else:
             arr[c] = trees[c]._struct()
     d, g, st = np.empty(n), np.empty((n, 3)), np.empty((n, 4))
-    s, p = scene._struct(), _params(alpha, alpha_u, beta, metric_r2)
+    s, p = scene._struct(), _params(alpha, alpha_u, beta, metric_r2, cut_f32)
     rc = lib().or_barnes_hut(ctypes.byref(s), ctypes.byref(p), arr, ctypes.c_int64(n), _ptr(Q),
                              _ptr(d), _ptr(g), _ptr(st))
     if rc != 0:

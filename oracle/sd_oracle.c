@@ -56,7 +56,7 @@ typedef struct {
 typedef struct {
     double alpha, alpha_u, beta;
     int32_t metric_r2;   /* 1: barycentric gradients measured in the alpha-scaled metric (Sec. 3.3) */
-    int32_t pad;
+    int32_t cut_f32;     /* 1: take the open/accept decision of Sec. 3.5 in FP32 (see accept_far) */
 } or_params;
 
 /* One exported hierarchy (one per primitive class). */
@@ -342,6 +342,29 @@ static int64_t count_leaves(const or_tree *tr, int32_t node, int64_t *out) {
     return c;
 }
 
+/* The Barnes-Hut opening test of Sec. 3.5: a node is taken as one far-field
+ * term iff its box diagonal |B| is below beta times the distance D from the
+ * query to the box.  It decides which terms enter the sum, so a comparison
+ * with a single-precision evaluator must take it in the same precision: with
+ * cut_f32 the test is made on squared lengths in FP32 (query and box corners
+ * rounded to FP32, each coordinate difference rounded, the sums of three
+ * squares formed as fma(x, x, fma(y, y, z * z)), beta^2 rounded to FP32,
+ * accept iff |B|^2 < beta^2 D^2).  Otherwise it is the FP64 test as written.
+ * Only the decision changes; every term is still evaluated in FP64. */
+static int accept_far(const or_params *p, const float *b, v3 q, double D, double diam) {
+    if (!p->cut_f32) return diam < p->beta * D;
+    float qx = (float)q.x, qy = (float)q.y, qz = (float)q.z;
+    float dx = qx - fminf(fmaxf(qx, b[0]), b[3]);
+    float dy = qy - fminf(fmaxf(qy, b[1]), b[4]);
+    float dz = qz - fminf(fmaxf(qz, b[2]), b[5]);
+    float ex = b[3] - b[0], ey = b[4] - b[1], ez = b[5] - b[2];
+    float D2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    float B2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+    float bf = (float)p->beta;
+    float beta2 = bf * bf;
+    return B2 < beta2 * D2;
+}
+
 static void collect(bh_ctx *cx, int32_t node) {
     const float *b = cx->tr->box + 6 * (int64_t)node;
     v3 lo = ld(b), hi = ld(b + 3), q = cx->q;
@@ -354,7 +377,7 @@ static void collect(bh_ctx *cx, int32_t node) {
         double m = fabs(cx->p->beta * D - diam) / D;
         if (m < cx->margin) cx->margin = m;
     }
-    if (diam < cx->p->beta * D) {
+    if (accept_far(cx->p, b, q, D, diam)) {
         /* far field: W_B exp(-alpha D) with W_B = n_B A^S, direction (q - y_B)/D */
         double logW = log((double)cx->nleaf[node]) + atten(cx->p) * cx->logA;
         push(cx->tl, logW - cx->p->alpha * D, scl(sub(q, y), 1.0 / D));

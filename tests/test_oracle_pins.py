@@ -644,3 +644,94 @@ def test_degenerate_triangle_is_its_longest_edge(oracle_mod):
     r = O.closest(2, V2.reshape(-1), q)
     s = O.closest(1, np.concatenate([V2[0], V2[2]]), q)
     assert abs(r["d"] - s["d"]) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.5: the opening decision taken in FP32 (the precision of the GPU path)
+# --------------------------------------------------------------------------
+def _f32(x):
+    """Round an exact rational to the nearest FP32 value (ties to even)."""
+    x = Fraction(x)
+    if x == 0:
+        return Fraction(0)
+    s, a = (-1 if x < 0 else 1), abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if a < Fraction(2) ** e:
+        e -= 1
+    m = a * Fraction(2) ** (23 - e)          # in [2^23, 2^24)
+    n = m.numerator // m.denominator
+    r = m - n
+    if r > Fraction(1, 2) or (r == Fraction(1, 2) and n % 2):
+        n += 1
+    return s * n * Fraction(2) ** (e - 23)
+
+
+def _fma32(a, b, c):
+    return _f32(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def _accept_f32_exact(q, lo, hi, beta):
+    """|B|^2 < beta^2 D^2 with every operation rounded to FP32 once, the sums
+    of squares as fma(x, x, fma(y, y, z*z)); computed in exact rationals."""
+    q = [Fraction(float(np.float32(v))) for v in q]
+    lo = [Fraction(float(v)) for v in lo]
+    hi = [Fraction(float(v)) for v in hi]
+    d = [_f32(q[i] - min(max(q[i], lo[i]), hi[i])) for i in range(3)]
+    e = [_f32(hi[i] - lo[i]) for i in range(3)]
+    D2 = _fma32(d[0], d[0], _fma32(d[1], d[1], _f32(d[2] * d[2])))
+    B2 = _fma32(e[0], e[0], _fma32(e[1], e[1], _f32(e[2] * e[2])))
+    bf = _f32(Fraction(beta))
+    return B2 < _f32(_f32(bf * bf) * D2)
+
+
+def test_fp32_cut_decision_pinned_by_exact_rounding(oracle_mod):
+    """Two points span the root box; queries lie on random rays at a distance
+    within a few FP32 ulps of the opening threshold |B| / beta.  The root is
+    one far term (1 far-field term in all) iff accepted, otherwise both point
+    leaves are far terms (2).  The FP32 mode must agree with the exactly
+    rounded FP32 test everywhere; the FP64 mode must differ from it somewhere
+    (so the queries do sit on rounding ties)."""
+    O = oracle_mod
+    rng = np.random.default_rng(41)
+    V = np.array([[0.1, -0.2, 0.3], [0.9, 0.35, -0.4]], np.float32)
+    sc = O.OracleScene(V, P=[0, 1])
+    trees = _otrees(O, sc)
+    box = trees[0].box[0]
+    lo, hi = box[:3].astype(np.float64), box[3:].astype(np.float64)
+    diam = np.linalg.norm(hi - lo)
+    Q, want = [], []
+    for beta in (0.1, 0.3, 0.7):
+        for _ in range(120):
+            u = rng.normal(size=3); u /= np.linalg.norm(u)
+            c = np.clip(hi + u, lo, hi)                       # some box point
+            D = diam / beta * (1 + rng.uniform(-3e-7, 3e-7))
+            q = np.float32(c + D * u / np.linalg.norm(u)).astype(np.float64)
+            Q.append((q, beta))
+    n32 = n64 = 0
+    for beta in (0.1, 0.3, 0.7):
+        qs = np.array([q for q, b in Q if b == beta])
+        _, _, s32 = O.barnes_hut(sc, trees, qs, 5.0, beta, cut_f32=True)
+        _, _, s64 = O.barnes_hut(sc, trees, qs, 5.0, beta)
+        exp = np.array([_accept_f32_exact(q, lo, hi, beta) for q in qs])
+        np.testing.assert_array_equal(s32[:, 2] == 1, exp)
+        n32 += len(qs)
+        n64 += int(np.sum((s64[:, 2] == 1) != exp))
+    assert n64 > 0, "no rounding tie among the queries"
+
+
+def test_fp32_cut_decision_equals_fp64_away_from_ties(oracle_mod):
+    """Where the FP64 margin |beta D - |B|| / D exceeds 1e-5 the two precisions
+    take the same decisions, so values, gradients and counts agree exactly."""
+    O = oracle_mod
+    V, T = _small_sphere(level=2, seed=8)
+    sc = O.OracleScene(V, T=T)
+    trees = _otrees(O, sc)
+    Q = np.random.default_rng(42).uniform(-2, 2, (400, 3)).astype(np.float32).astype(np.float64)
+    for alpha, beta in ((20.0, 0.5), (200.0, 1.0)):
+        d6, g6, s6 = O.barnes_hut(sc, trees, Q, alpha, beta)
+        d3, g3, s3 = O.barnes_hut(sc, trees, Q, alpha, beta, cut_f32=True)
+        ok = s6[:, 0] > 1e-5
+        assert ok.mean() > 0.95
+        np.testing.assert_array_equal(d3[ok], d6[ok])
+        np.testing.assert_array_equal(g3[ok], g6[ok])
+        np.testing.assert_array_equal(s3[ok, 1:], s6[ok, 1:])
