@@ -30,8 +30,8 @@ ALU_PEAK_PACKED_TFLOPS = 157.3
 # algorithmic FLOPs per unit of work, value + gradient, counted from the kernel's arithmetic:
 F_QUERY = 50        # load, seed bookkeeping, finalisation
 F_NODE = 26         # box distance, box diagonal, opening and pruning tests
-F_FAR = 35          # sqrt, rcp, direction, exponent, compensated sums
-F_TRI_LEAF = 636    # distance + region, de Casteljau weight, gradient, sums
+F_FAR = 23          # sqrt, rcp, direction, exponent, FP64 sums (1 add + 3 FMA)
+F_TRI_LEAF = 624    # distance + region, de Casteljau weight, gradient, FP64 sums
 METRIC = "smooth-distance+grad queries/s on 1 MI355X: BH vs surrogate at ≤1e-5 rel / 1e-3 abs"
 # algorithmic bytes per unit of work: query in, outputs out, node and leaf records read
 B_QUERY = 12 + 16 + 4        # query in, value + gradient out, order index

@@ -94,7 +94,8 @@ typedef struct sd_scene_info {
  * (Morton order, one primitive per leaf) is built per non-empty class.
  * Inputs are copied; the caller may free them once the call returns.
  * Errors: SD_EINVAL for negative sizes, null pointers with a positive count or
- * indices outside [0, nV); SD_EUNSUPPORTED for a triangle valence above 1023.
+ * indices outside [0, nV); SD_EUNSUPPORTED for a triangle valence above 1023
+ * or more than 2^26 primitives in one class.
  */
 int sd_build_bvh(const float *V, int64_t nV,
                  const int32_t *P, int64_t nP,

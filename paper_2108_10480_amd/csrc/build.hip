@@ -370,7 +370,8 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
                        int64_t n, const float *wt, hipStream_t s, Reduce *red_dev,
                        Reduce *red_host, const int32_t *tri_cls = nullptr) {
     if (n <= 0) return SD_OK;
-    if (n > (int64_t)0x3fffffff) return fail(SD_EUNSUPPORTED, "more than 2^30 primitives in a class");
+    // node records are addressed with 32-bit byte offsets: 2n - 1 nodes x 32 B < 2^32
+    if (n > ((int64_t)1 << 26)) return fail(SD_EUNSUPPORTED, "more than 2^26 primitives in a class");
     int64_t nn = 2 * n - 1;
     float4 *plo, *phi, *blo, *bhi;
     uint64_t *keys, *keys2;

@@ -10,7 +10,9 @@
 //
 // Online log-sum-exp state per lane: the distance d* and log-weight l* of the
 // largest term so far, the sum s of exp(L_i - L*) and the gradient numerator
-// G, both with Kahan compensation.  Exponents are formed as
+// G, both accumulated in FP64 (the terms are FP32; an FP64 add or FMA issues at
+// the rate of an FP32 one on this GPU, so this is cheaper than compensated
+// FP32 sums and more accurate).  Exponents are formed as
 // alpha (d* - d_i) + (l_i - l*), so large alpha d never overflows and no
 // precision is lost to the magnitude of alpha d.  d = d* - (l* + log s)/alpha.
 #include <math.h>
@@ -45,18 +47,9 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ float fdiv(float a, float b) { return a * frcp(b); }
 
 struct LSE {
-    float dref, lref, s, sc;
-    float gx, gy, gz, cx, cy, cz;
+    float dref, lref;
+    double s, gx, gy, gz;
 };
-
-// Compensated (Kahan) accumulation: the running sum is s + c, where c carries
-// the low-order part lost by the last addition.  Four FLOPs per term.
-__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
-    float y = x + c;
-    float t = s + y;
-    c = y - (t - s);
-    s = t;
-}
 
 // clamp(q, lo, hi) in one v_med3_f32 (lo <= hi for every box)
 __device__ __forceinline__ float clampf(float q, float lo, float hi) {
@@ -68,24 +61,20 @@ __device__ __forceinline__ void lse_add(LSE &st, float d, float lw, float gx, fl
                                         float alpha) {
     float t = fmaf(alpha, st.dref - d, lw - st.lref);   // L_i - L*
     if (t <= 0.f) {
-        float e = __expf(t);
-        kahan_add(st.s, st.sc, e);
+        double e = (double)__expf(t);
+        st.s += e;
         if (GRAD) {
-            kahan_add(st.gx, st.cx, e * gx);
-            kahan_add(st.gy, st.cy, e * gy);
-            kahan_add(st.gz, st.cz, e * gz);
+            st.gx = fma(e, (double)gx, st.gx);
+            st.gy = fma(e, (double)gy, st.gy);
+            st.gz = fma(e, (double)gz, st.gz);
         }
     } else {
-        float e = __expf(-t);
-        st.s *= e;
-        st.sc *= e;
-        kahan_add(st.s, st.sc, 1.f);
+        double e = (double)__expf(-t);
+        st.s = fma(st.s, e, 1.0);
         if (GRAD) {
-            st.gx *= e; st.gy *= e; st.gz *= e;
-            st.cx *= e; st.cy *= e; st.cz *= e;
-            kahan_add(st.gx, st.cx, gx);
-            kahan_add(st.gy, st.cy, gy);
-            kahan_add(st.gz, st.cz, gz);
+            st.gx = fma(st.gx, e, (double)gx);
+            st.gy = fma(st.gy, e, (double)gy);
+            st.gz = fma(st.gz, e, (double)gz);
         }
         st.dref = d;
         st.lref = lw;
@@ -383,10 +372,13 @@ __device__ __forceinline__ int node_test(const TreeView &T, const EvalArgs &A, f
     }
     if (diag2 < A.beta2 * D2) {
         // far field at the closest box point y_B: weight n_B A^S (App. D)
+        // D > 0 here: the test passed, so D^2 > |B|^2 / beta^2 >= 0.  The
+        // distance enters rounded down by D 2^-21 (one rounding of
+        // D (1 - 2^-21), a representable factor).
         float D = fsqrt(D2);
-        float inv = D > 0.f ? frcp(D) : 0.f;
+        float inv = frcp(D);
         float lw = logn + T.slogA;
-        lse_add<GRAD>(st, fmaf(-A.cons, D * 0x1p-21f, D), lw, dx * inv, dy * inv, dz * inv, A.alpha);
+        lse_add<GRAD>(st, D * A.far_scale, lw, dx * inv, dy * inv, dz * inv, A.alpha);
         if (COUNT) ++n_far;
         node = esc;
     } else if (pay < 0) {
@@ -403,8 +395,14 @@ template <bool GRAD, bool COUNT, bool PRUNE>
 __device__ __forceinline__ int node_step(const TreeView &T, const EvalArgs &A, float qx, float qy,
                                          float qz, LSE &st, int &node, float4 &leaf_lo, int &n_vis,
                                          int &n_far) {
-    return node_test<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, T.lo[2 * node], T.hi[2 * node], node, leaf_lo,
-                                  n_vis, n_far);
+    // a node record is 32 B (lo, hi); a 32-bit byte offset from the array base
+    // gives the loads' scalar-base + vector-offset form (node counts stay far
+    // below 2^27, which the build checks)
+    const char *base = reinterpret_cast<const char *>(T.lo);
+    uint32_t off = static_cast<uint32_t>(node) << 5;
+    float4 lo = *reinterpret_cast<const float4 *>(base + off);
+    float4 hi = *reinterpret_cast<const float4 *>(base + off + 16);
+    return node_test<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, lo, hi, node, leaf_lo, n_vis, n_far);
 }
 
 // Alg. 1 over one class hierarchy, stackless (escape indices).  Exact leaf
@@ -471,7 +469,7 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
     const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
     int node = T.n_nodes > 0 ? 0 : -1;
     float4 leaf_lo = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (node >= 0 && st.s == 0.f && st.dref == INFINITY) {
+    if (node >= 0 && st.s == 0.0 && st.dref == INFINITY) {
         float sd = seed_distance(T, qx, qy, qz, A.inv_alpha);
         if (sd == sd) {   // NaN queries keep the empty reference
             st.dref = sd;
@@ -498,18 +496,26 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     int cnt = 0;
     while (true) {
-        while (true) {
-            bool can = node >= 0 && cnt < kQ;
-            if (__ballot(can) == 0) break;
-            if (__ballot(node >= 0 && cnt >= kQ)) break;   // flush before a lane stalls
-            if (can) {
-                int slot = node_step<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
-                if (slot >= 0) {
-                    lq.slot[cnt][lane] = slot;
-                    ++cnt;
-                    if (COUNT) ++n_leaf;
+        // Node steps until no lane can continue or some lane's queue is full
+        // (flush before a lane stalls).  The loop condition is wave-uniform
+        // and tested at the bottom through readfirstlane, so the loop exits
+        // uniformly: the compiler then keeps the sum state in place instead of
+        // copying it out for lanes that leave early on every iteration.
+        bool can = node >= 0 && cnt < kQ;
+        int go = __ballot(can) != 0 && __ballot(node >= 0 && cnt >= kQ) == 0;
+        if (__builtin_amdgcn_readfirstlane(go)) {
+            do {
+                if (can) {
+                    int slot = node_step<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
+                    if (slot >= 0) {
+                        lq.slot[cnt][lane] = slot;
+                        ++cnt;
+                        if (COUNT) ++n_leaf;
+                    }
                 }
-            }
+                can = node >= 0 && cnt < kQ;
+                go = __ballot(can) != 0 && __ballot(node >= 0 && cnt >= kQ) == 0;
+            } while (__builtin_amdgcn_readfirstlane(go));
         }
         if (__ballot(cnt > 0) == 0) break;
         // exclusive prefix of the per-lane counts (kQ <= 7: three bit planes)
@@ -566,28 +572,31 @@ __device__ __forceinline__ int xcd_block(int i, int G) {
 
 template <bool GRAD>
 __device__ __forceinline__ void finalize(const EvalArgs &A, const LSE &st, int qi) {
-    float sum = st.s + st.sc;
+    float sum = (float)st.s;
     float d, gx = 0.f, gy = 0.f, gz = 0.f;
     if (!(sum > 0.f) && !(sum != sum)) {
         d = INFINITY;   // empty scene: the empty sum
     } else {
-        float corr;
+        // |lref| + |log sum| bounds the magnitudes the correction is formed from
+        float mag;
         if (A.flags & SD_ROOTLOG_F64) {
-            double s64 = (double)st.s + (double)st.sc;
-            double dd = (double)st.dref - ((double)st.lref + log(s64)) * (double)A.inv_alpha;
-            corr = (float)((double)st.dref - dd);
+            double s64 = st.s;
+            double ls = log(s64);
+            double dd = (double)st.dref - ((double)st.lref + ls) * (double)A.inv_alpha;
+            mag = (float)((fabs((double)st.lref) + fabs(ls)) * (double)A.inv_alpha);
             d = (float)dd;
         } else {
-            corr = (st.lref + logf(sum)) * A.inv_alpha;
-            d = st.dref - corr;
+            float ls = logf(sum);
+            d = st.dref - (st.lref + ls) * A.inv_alpha;
+            mag = (fabsf(st.lref) + fabsf(ls)) * A.inv_alpha;
         }
         if (!(A.flags & SD_NO_CONSERVATIVE_ROUNDING))
-            d -= A.margin_scale * (fabsf(st.dref) + fabsf(corr));
+            d -= A.margin_scale * (fabsf(st.dref) + mag);
         if (GRAD) {
             float inv = 1.f / sum;
-            gx = (st.gx + st.cx) * inv;
-            gy = (st.gy + st.cy) * inv;
-            gz = (st.gz + st.cz) * inv;
+            gx = (float)st.gx * inv;
+            gy = (float)st.gy * inv;
+            gz = (float)st.gz * inv;
         }
     }
     A.d_out[qi] = d;
@@ -599,8 +608,8 @@ __device__ __forceinline__ void finalize(const EvalArgs &A, const LSE &st, int q
 }
 
 __device__ __forceinline__ void lse_init(LSE &st) {
-    st.dref = INFINITY; st.lref = 0.f; st.s = 0.f; st.sc = 0.f;
-    st.gx = st.gy = st.gz = st.cx = st.cy = st.cz = 0.f;
+    st.dref = INFINITY; st.lref = 0.f;
+    st.s = st.gx = st.gy = st.gz = 0.0;
 }
 
 // Waves per SIMD the traversal is compiled for (register budget); the
@@ -793,6 +802,7 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
     A.S = (float)S;
     A.margin_scale = ldexpf(1.f, -22);
     A.cons = (p->flags & SD_NO_CONSERVATIVE_ROUNDING) ? 0.f : 1.f;
+    A.far_scale = (p->flags & SD_NO_CONSERVATIVE_ROUNDING) ? 1.f : 1.f - 0x1p-21f;
     A.defer = defer_threshold();
     A.prune = 64.f;
     A.flags = p->flags;

@@ -62,6 +62,7 @@ struct EvalArgs {
     float alpha, inv_alpha, beta2, S;
     float margin_scale;   // final rounding margin: 2^-22 (|d*| + |log-sum term|)
     float cons;           // 1: each term enters at its rounded-down distance (default)
+    float far_scale;      // far-field distance factor: 1 - 2^-21 with cons, else 1
     int32_t defer;        // 1: wave-cooperative leaf stage, 0: leaves evaluated inline
     float prune;          // skip subtrees whose terms are below exp(-prune) of the reference
     uint32_t flags;
