@@ -336,16 +336,25 @@ __device__ __forceinline__ Term leaf_term(const TreeView &T, const EvalArgs &A, 
 
 // One node of Alg. 1: the opening test, then the far-field term (App. D) or a
 // leaf hand-off or descent.  Returns the leaf slot to evaluate, or -1.
-template <bool GRAD, bool COUNT, bool PRUNE>
-__device__ __forceinline__ int node_step(const TreeView &T, const EvalArgs &A, float qx, float qy,
-                                         float qz, LSE &st, int &node, float4 &leaf_lo, int &n_vis,
-                                         int &n_far);
+// a node record is 32 B (lo, hi); a 32-bit byte offset from the array base
+// gives the loads' scalar-base + vector-offset form (node counts stay far
+// below 2^27, which the build checks)
+__device__ __forceinline__ void load_node(const TreeView &T, int node, float4 &lo, float4 &hi) {
+    const char *base = reinterpret_cast<const char *>(T.lo);
+    uint32_t off = static_cast<uint32_t>(node) << 5;
+    lo = *reinterpret_cast<const float4 *>(base + off);
+    hi = *reinterpret_cast<const float4 *>(base + off + 16);
+}
 
-// node_step on a node whose record (lo, hi) is already in registers
+// One step of Alg. 1 on `node`, whose record (lo, hi) is in registers: the
+// opening test, then the next node (escape after a far-field term or a leaf,
+// else the left child node + 1), whose record is loaded into (lo, hi) before
+// the far-field term is added, so that the load overlaps that arithmetic.
+// Returns the leaf slot to evaluate, or -1.
 template <bool GRAD, bool COUNT, bool PRUNE>
-__device__ __forceinline__ int node_test(const TreeView &T, const EvalArgs &A, float qx, float qy,
-                                         float qz, LSE &st, float4 lo, float4 hi, int &node,
-                                         float4 &leaf_lo, int &n_vis, int &n_far) {
+__device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, float qx, float qy,
+                                          float qz, LSE &st, float4 &lo, float4 &hi, int &node,
+                                          float4 &leaf_lo, int &n_vis, int &n_far) {
     float yx = clampf(qx, lo.x, hi.x);
     float yy = clampf(qy, lo.y, hi.y);
     float yz = clampf(qz, lo.z, hi.z);
@@ -356,53 +365,40 @@ __device__ __forceinline__ int node_test(const TreeView &T, const EvalArgs &A, f
     int esc = __float_as_int(lo.w);
     int pay = __float_as_int(hi.w);
     if (COUNT) ++n_vis;
-    int slot = -1;
     float logn = pay < 0 ? 0.f : hi.w;
     // Negligible subtree: every term below this node is at most
     // n_B W_max exp(-alpha D) (D <= each d_i), i.e. its exponent relative to
     // the running reference is below -A.prune (64: < 1e-27 of the sum), so it
     // cannot change the FP32 result; skip it.  D > d* + (log n_B + log W_max
     // - l* + prune)/alpha, tested on squares.
+    bool skip = false;
     if (PRUNE) {
         float thr = fmaf(logn + T.lwmax - st.lref + A.prune, A.inv_alpha, st.dref);
-        if (thr < 0.f || D2 > thr * thr) {
-            node = esc;
-            return -1;
-        }
+        skip = thr < 0.f || D2 > thr * thr;
     }
-    if (diag2 < A.beta2 * D2) {
-        // far field at the closest box point y_B: weight n_B A^S (App. D)
+    bool far = !skip && diag2 < A.beta2 * D2;
+    bool leaf = !skip && !far && pay < 0;
+    int slot = -1;
+    if (leaf) {
+        slot = pay & 0x7fffffff;
+        leaf_lo = lo;
+    }
+    node = (skip || far || leaf) ? esc : node + 1;
+    if (node >= 0) load_node(T, node, lo, hi);
+    if (far) {
+        // far field at the closest box point y_B: weight n_B A^S (App. D).
         // D > 0 here: the test passed, so D^2 > |B|^2 / beta^2 >= 0.  The
         // distance enters rounded down by D 2^-21 (one rounding of
-        // D (1 - 2^-21), a representable factor).
+        // D (1 - 2^-21), a representable factor).  (D = D^2 rsq(D^2) would
+        // save a transcendental, but its 2-3 ulp error shows in gradients at
+        // large alpha.)
         float D = fsqrt(D2);
         float inv = frcp(D);
         float lw = logn + T.slogA;
         lse_add<GRAD>(st, D * A.far_scale, lw, dx * inv, dy * inv, dz * inv, A.alpha);
         if (COUNT) ++n_far;
-        node = esc;
-    } else if (pay < 0) {
-        slot = pay & 0x7fffffff;
-        leaf_lo = lo;
-        node = esc;
-    } else {
-        node = node + 1;
     }
     return slot;
-}
-
-template <bool GRAD, bool COUNT, bool PRUNE>
-__device__ __forceinline__ int node_step(const TreeView &T, const EvalArgs &A, float qx, float qy,
-                                         float qz, LSE &st, int &node, float4 &leaf_lo, int &n_vis,
-                                         int &n_far) {
-    // a node record is 32 B (lo, hi); a 32-bit byte offset from the array base
-    // gives the loads' scalar-base + vector-offset form (node counts stay far
-    // below 2^27, which the build checks)
-    const char *base = reinterpret_cast<const char *>(T.lo);
-    uint32_t off = static_cast<uint32_t>(node) << 5;
-    float4 lo = *reinterpret_cast<const float4 *>(base + off);
-    float4 hi = *reinterpret_cast<const float4 *>(base + off + 16);
-    return node_test<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, lo, hi, node, leaf_lo, n_vis, n_far);
 }
 
 // Alg. 1 over one class hierarchy, stackless (escape indices).  Exact leaf
@@ -476,14 +472,23 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
             st.lref = 0.f;
         }
     }
+    // (lo, hi): the record of `node` while node >= 0, loaded one step ahead
+    float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+    if (node >= 0) load_node(T, node, lo, hi);
     if (CLS == 0 || A.defer == 0) {
-        while (node >= 0) {
-            int slot = node_step<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
-            if (slot >= 0) {
-                if (COUNT) ++n_leaf;
-                Term t = leaf_term<CLS, GRAD>(T, A, slot, leaf_lo, qx, qy, qz, metric);
-                lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
-            }
+        // leaves inline; the loop condition is a wave-uniform mask (see below)
+        if (__builtin_amdgcn_sicmp(node, 0, 39 /* >= */) != 0) {
+            do {
+                if (node >= 0) {
+                    int slot = node_visit<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, lo, hi, node, leaf_lo,
+                                                              n_vis, n_far);
+                    if (slot >= 0) {
+                        if (COUNT) ++n_leaf;
+                        Term t = leaf_term<CLS, GRAD>(T, A, slot, leaf_lo, qx, qy, qz, metric);
+                        lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
+                    }
+                }
+            } while (__builtin_amdgcn_sicmp(node, 0, 39) != 0);
         }
         return;
     }
@@ -497,25 +502,29 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
     int cnt = 0;
     while (true) {
         // Node steps until no lane can continue or some lane's queue is full
-        // (flush before a lane stalls).  The loop condition is wave-uniform
-        // and tested at the bottom through readfirstlane, so the loop exits
+        // (flush before a lane stalls).  The condition is formed from two
+        // compare masks (lanes with a node left, lanes with queue room; no
+        // ballot materialisation) and tested at the bottom, so the loop exits
         // uniformly: the compiler then keeps the sum state in place instead of
-        // copying it out for lanes that leave early on every iteration.
-        bool can = node >= 0 && cnt < kQ;
-        int go = __ballot(can) != 0 && __ballot(node >= 0 && cnt >= kQ) == 0;
-        if (__builtin_amdgcn_readfirstlane(go)) {
+        // copying it out, on every iteration, for lanes that might leave early.
+        uint64_t live = __builtin_amdgcn_sicmp(node, 0, 39 /* >= */);
+        uint64_t room = __builtin_amdgcn_sicmp(cnt, kQ, 40 /* < */);
+        bool go = ((live & room) != 0) & ((live & ~room) == 0);
+        if (go) {
             do {
-                if (can) {
-                    int slot = node_step<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, node, leaf_lo, n_vis, n_far);
+                if (node >= 0 && cnt < kQ) {
+                    int slot = node_visit<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, lo, hi, node, leaf_lo,
+                                                              n_vis, n_far);
                     if (slot >= 0) {
                         lq.slot[cnt][lane] = slot;
                         ++cnt;
                         if (COUNT) ++n_leaf;
                     }
                 }
-                can = node >= 0 && cnt < kQ;
-                go = __ballot(can) != 0 && __ballot(node >= 0 && cnt >= kQ) == 0;
-            } while (__builtin_amdgcn_readfirstlane(go));
+                live = __builtin_amdgcn_sicmp(node, 0, 39);
+                room = __builtin_amdgcn_sicmp(cnt, kQ, 40);
+                go = ((live & room) != 0) & ((live & ~room) == 0);
+            } while (go);
         }
         if (__ballot(cnt > 0) == 0) break;
         // exclusive prefix of the per-lane counts (kQ <= 7: three bit planes)
