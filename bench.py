@@ -344,9 +344,10 @@ def rigid_leg(args, np, torch, api, scenes):
     """Differentiable rigid-body step on the mixed street scene: 256 rigid
     transforms of a 25,000-vertex torus (6.4M queries) against 2M points,
     20,000 wire segments and the 50,000-triangle torus at rest; forward
-    (transform, order, Barnes-Hut value+gradient) and the hand-written adjoint
-    in (R, t, X) for an upstream gradient."""
-    alpha, beta = 50.0, 0.5
+    (transform, order, Barnes-Hut value+gradient, the query-mesh distance
+    D_k of each placement, Eq. 6) and the hand-written adjoint of sum_k D_k
+    in (R, t, X)."""
+    alpha, beta, alpha_q = 50.0, 0.5, 50.0
     ev = lambda: torch.cuda.Event(enable_timing=True)
     sc, body = scenes.street_scene(1.0)
     t0 = time.perf_counter()
@@ -359,7 +360,6 @@ def rigid_leg(args, np, torch, api, scenes):
     td = torch.as_tensor(t, device="cuda")
     K, m = R.shape[0], body.shape[0]
     n = K * m
-    gbar = torch.as_tensor(np.random.default_rng(9).normal(size=(K, m)).astype(np.float32), device="cuda")
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     d = torch.empty(n, device="cuda")
     g = torch.empty((n, 3), device="cuda")
@@ -372,22 +372,28 @@ def rigid_leg(args, np, torch, api, scenes):
         api.sd_query_order(scene, Q, out=perm)
         api.sd_eval_grad_ordered(scene, Q, perm, alpha, beta, out=d, grad_out=g)
         if evs: evs[2].record()
-        out = api.sd_rigid_adjoint(X, Rd, gbar, g)
+        # D_k and dD_k/dd_kj; dL/dD_k = 1 for L = sum_k D_k
+        D, w, _ = api.sd_query_mesh_lse(d.reshape(K, m), None, alpha_q, want_vgrad=False)
         if evs: evs[3].record()
-        return Q, out
+        out = api.sd_rigid_adjoint(X, Rd, w, g)
+        if evs: evs[4].record()
+        return Q, D, out
 
     step()
     torch.cuda.synchronize()
-    evs = [[ev() for _ in range(4)] for _ in range(args.rigid_steps)]
+    evs = [[ev() for _ in range(5)] for _ in range(args.rigid_steps)]
     a, b = ev(), ev()
     a.record()
     for k in range(args.rigid_steps):
-        Q, _ = step(evs[k])
+        Q, Dk, _ = step(evs[k])
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / args.rigid_steps
     st = lambda i, j: float(np.mean([e[i].elapsed_time(e[j]) for e in evs]))
-    ms_adj = st(2, 3)
+    ms_adj = st(3, 4)
+    ms_qm = st(2, 3)
+    # query-mesh pass: d read three times (minimum, sum, weights), w written
+    qm_bytes = n * 16
     cnt = api.sd_eval_counters(scene, Q[:200000].contiguous(), alpha, beta).double().mean(0).cpu().numpy()
     adj_bytes = n * (4 + 12) + m * 12 + K * (9 + 3) * 4 * 2
     res = {
@@ -395,8 +401,13 @@ def rigid_leg(args, np, torch, api, scenes):
                     f"{sc.counts()[2]} torus triangles; {K} rigid transforms x {m} body vertices = {n} "
                     f"queries, alpha={alpha:g}, beta={beta:g}, value+gradient and adjoint in (R, t, X)",
         "value": n / (ms * 1e-3), "unit": "queries/s (forward + adjoint)", "ms_per_step": ms,
-        "stages_ms": {"transform": st(0, 1), "order_and_traversal": st(1, 2), "adjoint": ms_adj,
-                      "build": build_ms},
+        "stages_ms": {"transform": st(0, 1), "order_and_traversal": st(1, 2), "query_mesh_lse": ms_qm,
+                      "adjoint": ms_adj, "build": build_ms},
+        "query_mesh": {"alpha_q": alpha_q, "instances": K, "D_min": float(Dk.min()), "D_max": float(Dk.max()),
+                       "roofline": {"bound": "hbm", "achieved": qm_bytes / (ms_qm * 1e-3) / 1e9,
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": qm_bytes / (ms_qm * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                    "bytes_per_query": 16, "traffic": None}},
         "work_per_query": {"nodes": float(cnt[0]), "far_terms": float(cnt[1]), "leaves": float(cnt[2])},
         "adjoint_roofline": {"bound": "hbm", "achieved": adj_bytes / (ms_adj * 1e-3) / 1e9,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -420,6 +431,15 @@ def rigid_leg(args, np, torch, api, scenes):
         res["parity_sample"] = {"n": len(dg), "max_err_vs_oracle": float(err.max()),
                                 "conservative_violations": int(np.sum(dg > dr)),
                                 "oracle_queries_per_s": len(idx) / dt}
+        # query-mesh distance of two whole placements against the oracle composite
+        from oracle import qmesh as QM
+        Qk = Q[: 2 * m].cpu().numpy().astype(np.float64)
+        dk, gk, _ = O.barnes_hut(osc, trees, Qk, alpha, beta, cut_f32=True)
+        Dr = QM.query_mesh_lse(dk.reshape(2, m), gk.reshape(2, m, 3), alpha_q)[0]
+        Dg = Dk[:2].cpu().numpy().astype(np.float64)
+        res["query_mesh"]["parity_sample"] = {
+            "instances": 2, "max_err_vs_oracle": float(np.max(np.abs(Dg - Dr) / np.maximum(np.abs(Dr), floor))),
+            "metric": "|D - D_oracle| / max(|D_oracle|, 1e-3 scene diagonal); d with the default conservative rounding"}
     return res
 
 

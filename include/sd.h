@@ -194,6 +194,37 @@ int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64_t K,
                      float *Rbar, float *tbar, float *Xbar, void *stream);
 
 /*
+ * Smooth distance between the data mesh and a query mesh (Sec. 3.6), for K
+ * instances of one query mesh (e.g. K rigid placements of a body): from the
+ * per-primitive smooth distances d (K x m, row k = instance k, as computed by
+ * sd_eval_grad for the instance's query primitives) and their gradients grad
+ * (K x m x 3),
+ *   D_k = -(1/alpha_q) log sum_j exp(-alpha_q d_kj)                  (Eq. 6),
+ *   w_kj = dD_k/dd_kj = exp(-alpha_q d_kj) / sum_j exp(-alpha_q d_kj),
+ *   vgrad_kv = sum over primitives g_j containing vertex v of
+ *              w_kj / (n(g_j) + 1) grad_kj                         (Eq. 7, Eq. 8):
+ * each exponential is split equally between the n(g_j) + 1 vertices of its
+ * primitive, whose gradient moves it rigidly.
+ * prim: m x 3 int32 vertex ids per query primitive (-1 for unused corners: a
+ * point has one vertex, an edge two, a triangle three), ids in [0, nV); or
+ * NULL when primitive j is vertex j (a point query mesh; nV is then m).
+ * All arrays are device memory.  Outputs: D (K), w (K x m, may be NULL),
+ * vgrad (K x nV x 3, may be NULL; grad may be NULL when vgrad is).
+ * The largest term is factored out and the sum is formed in FP64 in a fixed
+ * order (D and w bitwise reproducible); vertex gradients of a general query
+ * mesh are added with atomics (summation order not fixed).  An instance with
+ * m = 0 or every d = +inf gives D = +inf, w = 0, vgrad = 0; a NaN distance
+ * makes its instance NaN.
+ * Errors: SD_EINVAL for alpha_q <= 0 or not finite, negative sizes, null
+ * pointers, primitive ids outside [0, nV) or a primitive without vertices
+ * (checked on the device; the call then synchronises the stream);
+ * SD_EUNSUPPORTED for K > 65535 or m > 2^28.
+ */
+int sd_query_mesh_lse(const float *d, const float *grad, int64_t K, int64_t m,
+                      const int32_t *prim, int64_t nV, float alpha_q,
+                      float *D, float *w, float *vgrad, void *stream);
+
+/*
  * Learned surrogate of the smooth distance.  The paper has no learned part:
  * this network approximates d of Eq. 3 for one scene and one (alpha, alpha_u,
  * beta, flags) setting, is trained on values the exact evaluation produces,

@@ -51,7 +51,7 @@ _lib = None
 EXPORTED = ["sd_build_bvh", "sd_free_scene", "sd_scene_info_get", "sd_eval", "sd_eval_grad",
             "sd_eval_brute", "sd_eval_counters", "sd_export_bvh", "sd_export_weights",
             "sd_query_order", "sd_eval_grad_ordered",
-            "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint",
+            "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint", "sd_query_mesh_lse",
             "sd_surrogate_create", "sd_surrogate_free", "sd_surrogate_forward",
             "sd_surrogate_loss_grad", "sd_surrogate_adam", "sd_surrogate_train_step",
             "sd_surrogate_certify", "sd_surrogate_certify_cells", "sd_surrogate_save", "sd_surrogate_load", "sd_eval_surrogate",
@@ -294,6 +294,71 @@ class RigidSmoothDistance(torch.autograd.Function):
 
 def rigid_smooth_distance(X, R, t, scene, alpha, beta=0.5, alpha_u=0.0, flags=0):
     return RigidSmoothDistance.apply(X, R, t, scene, alpha, beta, alpha_u, flags)
+
+
+def sd_query_mesh_lse(d, grad, alpha_q, prim=None, nV=None, want_w=True, want_vgrad=True):
+    """Smooth distance to a query mesh (Sec. 3.6, Eq. 6-8) for K instances:
+    d (K, m) per-primitive distances, grad (K, m, 3) their gradients, prim
+    (m, 3) int32 vertex ids (-1 unused) or None for a point query mesh.
+    Returns (D (K,), w (K, m) or None, vgrad (K, nV, 3) or None)."""
+    if d.dim() != 2:
+        raise ValueError("d must be K x m")
+    K, m = d.shape
+    dc = d.contiguous()
+    if dc.dtype != torch.float32 or not dc.is_cuda:
+        raise ValueError("d must be a float32 CUDA tensor")
+    gp = 0
+    if want_vgrad:
+        gc = grad.reshape(K, m, 3).contiguous()
+        if gc.dtype != torch.float32 or not gc.is_cuda:
+            raise ValueError("grad must be a float32 CUDA tensor")
+        gp = gc.data_ptr()
+    pp = 0
+    if prim is not None:
+        pc = prim.contiguous()
+        if pc.dtype != torch.int32 or not pc.is_cuda or pc.shape != (m, 3):
+            raise ValueError("prim must be an m x 3 int32 CUDA tensor")
+        pp = pc.data_ptr()
+        if nV is None:
+            raise ValueError("nV is required with prim")
+    else:
+        nV = m
+    D = torch.empty(K, dtype=torch.float32, device=d.device)
+    w = torch.empty((K, m), dtype=torch.float32, device=d.device) if want_w else None
+    vg = torch.empty((K, nV, 3), dtype=torch.float32, device=d.device) if want_vgrad else None
+    _check(lib().sd_query_mesh_lse(_c_p(dc.data_ptr()), _c_p(gp), _i64(K), _i64(m), _c_p(pp), _i64(nV),
+                                   ctypes.c_float(alpha_q), _c_p(D.data_ptr()),
+                                   _c_p(w.data_ptr() if w is not None else 0),
+                                   _c_p(vg.data_ptr() if vg is not None else 0), _stream()))
+    return D, w, vg
+
+
+class RigidQueryMeshDistance(torch.autograd.Function):
+    """D_k = smooth distance between the data mesh and the point query mesh
+    {R_k x_j + t_k} (Eq. 6 with alpha_q), differentiable in (R, t, X): the
+    upstream dL/dD_k times the weights w_kj = dD_k/dd_kj feeds the rigid
+    adjoint (sd_rigid_adjoint)."""
+
+    @staticmethod
+    def forward(ctx, X, R, t, scene, alpha, beta, alpha_u, flags, alpha_q):
+        Xc, Rc, tc = X.detach().contiguous(), R.detach().contiguous(), t.detach().contiguous()
+        Q = sd_rigid_transform(Xc, Rc, tc)
+        d, g = sd_eval_grad(scene, Q, alpha, beta, alpha_u, flags)
+        K, m = Rc.reshape(-1, 9).shape[0], Xc.shape[0]
+        D, w, _ = sd_query_mesh_lse(d.reshape(K, m), None, alpha_q, want_vgrad=False)
+        ctx.save_for_backward(Xc, Rc, g, w)
+        return D
+
+    @staticmethod
+    def backward(ctx, Dbar):
+        X, R, g, w = ctx.saved_tensors
+        gbar = (w * Dbar.reshape(-1, 1)).contiguous()
+        Rbar, tbar, Xbar = sd_rigid_adjoint(X, R, gbar, g, want_x=ctx.needs_input_grad[0])
+        return (Xbar, Rbar.reshape(R.shape), tbar, None, None, None, None, None, None)
+
+
+def rigid_query_mesh_distance(X, R, t, scene, alpha, alpha_q, beta=0.5, alpha_u=0.0, flags=0):
+    return RigidQueryMeshDistance.apply(X, R, t, scene, alpha, beta, alpha_u, flags, alpha_q)
 
 
 def upload_scene(sc, device="cuda", flags=0):

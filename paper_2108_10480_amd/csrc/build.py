@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "libsd.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "build.hip", "eval.hip", "sort.hip", "rigid.hip", "weights.cpp", "mlp.hip"]
+SOURCES = ["api.hip", "build.hip", "eval.hip", "sort.hip", "rigid.hip", "qmesh.hip", "weights.cpp", "mlp.hip"]
 ARCH = os.environ.get("SD_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of the device code
