@@ -78,6 +78,11 @@ def main():
                     help="also run the alpha / precision sweep on the terrain + mesh scene")
     ap.add_argument("--sweep-scale", type=float, default=0.1,
                     help="size of the sweep scene relative to 20M points, 1M triangles, 200k edges, 32M queries")
+    ap.add_argument("--beta-ablation", action="store_true",
+                    help="sphere-trace renders of vertex, edge and triangle scenes over beta (Sec. 4.3 analogue)")
+    ap.add_argument("--ablation-res", type=int, default=256, help="image side of the beta ablation renders")
+    ap.add_argument("--switch-study", action="store_true",
+                    help="near/far switch discrepancy beta 0.5 vs 0.5001 on the street points (Sec. 4.3 analogue)")
     ap.add_argument("--sur-train", type=int, default=20_000_000, help="surrogate training samples")
     ap.add_argument("--sur-epochs", type=int, default=80)
     ap.add_argument("--sur-nq", type=int, default=16_000_000, help="surrogate inference queries")
@@ -272,7 +277,121 @@ def main():
         out["rigid"] = rigid_leg(args, np, torch, api, scenes)
     if args.sweep:
         out["precision_sweep"] = sweep_leg(args, np, torch, api, scenes)
+    if args.beta_ablation:
+        out["beta_ablation"] = beta_ablation_leg(args, np, torch, api, scenes)
+    if args.switch_study:
+        out["switch_study"] = switch_study_leg(args, np, torch, api, scenes)
     print(json.dumps(out))
+
+
+def _camera_rays(np, res, eye, fov_deg=40.0):
+    """Pinhole camera at eye looking at the origin: res x res unit rays."""
+    eye = np.asarray(eye, np.float64)
+    f = -eye / np.linalg.norm(eye)
+    r = np.cross(f, [0.0, 0.0, 1.0])
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    s = np.tan(np.radians(fov_deg) / 2)
+    g = (np.arange(res) + 0.5) / res * 2 - 1
+    px, py = np.meshgrid(g * s, -g * s)
+    D = f[None] + px.reshape(-1, 1) * r[None] + py.reshape(-1, 1) * u[None]
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    return np.tile(eye, (len(D), 1)).astype(np.float32), D.astype(np.float32)
+
+
+def beta_ablation_leg(args, np, torch, api, scenes):
+    """Synthetic analogue of the beta ablation (Sec. 4.3): sphere-trace the zero
+    isosurface of the vertices, the edges and the triangles of a bumpy
+    icosphere (level 5: 10,242 vertices, 30,720 edges, 20,480 triangles) with
+    alpha 200, alpha_U 1200; render time per beta and the distance along each
+    ray between the beta isosurface and the exact one (beta = 0), relative to
+    the bounding-box diagonal."""
+    mesh = scenes.bumpy_icosphere(level=5, seed=2)
+    V, T = mesh.V, mesh.T
+    E = np.unique(np.sort(np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]]), axis=1), axis=0).astype(np.int32)
+    lo, hi = V.min(0), V.max(0)
+    diag = float(np.linalg.norm(hi - lo))
+    res = args.ablation_res
+    Oo, U = _camera_rays(np, res, (0.0, -3.2, 1.2))
+    Od, Ud = torch.as_tensor(Oo, device="cuda"), torch.as_tensor(U, device="cuda")
+    betas = [0.0, 0.1, 0.2, 0.3, 0.5, 0.75, 1.0]
+    alpha, alpha_u = 200.0, 1200.0
+    kw = dict(level=0.0, eps=1e-4 * diag, t_max=8.0, max_steps=1000)
+    out = {"workload": f"bumpy icosphere level 5 ({len(V)} vertices, {len(E)} edges, {len(T)} triangles), "
+                       f"{res}x{res} rays, alpha={alpha:g}, alpha_U={alpha_u:g}, eps={kw['eps']:.2g}",
+           "bbox_diagonal": diag, "scenes": {}}
+    for name, sc in (("vertices", scenes.Scene(V=V, P=np.arange(len(V), dtype=np.int32))),
+                     ("edges", scenes.Scene(V=V, E=E)), ("triangles", scenes.Scene(V=V, T=T))):
+        scene = api.upload_scene(sc)
+        rows, t0 = {}, None
+        for beta in betas:
+            api.sd_sphere_trace(scene, Od, Ud, alpha, beta, alpha_u, **kw)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            t, st = api.sd_sphere_trace(scene, Od, Ud, alpha, beta, alpha_u, **kw)
+            b.record()
+            torch.cuda.synchronize()
+            t = t.cpu().numpy().astype(np.float64)
+            row = {"ms": a.elapsed_time(b), "hits": int(np.isfinite(t).sum()),
+                   "mean_steps": float(st.double().mean())}
+            if t0 is None:
+                t0 = t
+            else:
+                both = np.isfinite(t) & np.isfinite(t0)
+                e = np.abs(t[both] - t0[both]) / diag
+                row.update({"speedup_vs_exact": rows["0"]["ms"] / row["ms"],
+                            "err_mean_rel_diag": float(e.mean()), "err_p99_rel_diag": float(np.quantile(e, 0.99)),
+                            "err_max_rel_diag": float(e.max()),
+                            "hit_mismatch": int(np.sum(np.isfinite(t) != np.isfinite(t0)))})
+            rows[f"{beta:g}"] = row
+        out["scenes"][name] = rows
+        scene.free()
+    return out
+
+
+def switch_study_leg(args, np, torch, api, scenes):
+    """Synthetic analogue of the near/far switch study (Sec. 4.3): on the street
+    scene's lidar-like points, trace vertical rays from the top of the box to
+    the 0.1 isosurface (beta 0.5), step on downwards, and wherever beta 0.5001
+    takes a different cut than beta 0.5 (fewer nodes visited) compare the two
+    values and gradients."""
+    sc, _ = scenes.street_scene(0.1)
+    pts = scenes.Scene(V=sc.V, P=sc.P)
+    scene = api.upload_scene(pts)
+    lo, hi = scenes.scene_aabb(pts)
+    diag = float(np.linalg.norm(hi - lo))
+    alpha, b0, b1 = 50.0, 0.5, 0.5001
+    rng = np.random.default_rng(11)
+    n = 65536
+    Oo = np.column_stack([rng.uniform(lo[0], hi[0], n), rng.uniform(lo[1], hi[1], n),
+                          np.full(n, hi[2] + 1.0)]).astype(np.float32)
+    U = np.tile(np.array([0.0, 0.0, -1.0], np.float32), (n, 1))
+    t, _ = api.sd_sphere_trace(scene, torch.as_tensor(Oo, device="cuda"), torch.as_tensor(U, device="cuda"),
+                               alpha, b0, level=0.1, eps=1e-4, t_max=float(hi[2] - lo[2] + 2.0), max_steps=2000)
+    t = t.cpu().numpy()
+    ok = np.isfinite(t)
+    P0 = Oo[ok] + t[ok, None] * U[ok]
+    h = 1e-3
+    Ps = np.concatenate([P0 + k * h * U[ok] for k in range(16)]).astype(np.float32)
+    Pd = torch.as_tensor(Ps, device="cuda")
+    c0 = api.sd_eval_counters(scene, Pd, alpha, b0).cpu().numpy()
+    c1 = api.sd_eval_counters(scene, Pd, alpha, b1).cpu().numpy()
+    d0, g0 = api.sd_eval_grad(scene, Pd, alpha, b0)
+    d1, g1 = api.sd_eval_grad(scene, Pd, alpha, b1)
+    d0, g0, d1, g1 = (x.cpu().numpy().astype(np.float64) for x in (d0, g0, d1, g1))
+    sw = c1[:, 0] < c0[:, 0]
+    dd = np.abs(d1[sw] - d0[sw])
+    cos = np.sum(g0[sw] * g1[sw], 1) / np.maximum(np.linalg.norm(g0[sw], axis=1) * np.linalg.norm(g1[sw], axis=1),
+                                                   1e-30)
+    scene.free()
+    return {"workload": f"street points ({len(sc.P)}), alpha={alpha:g}, vertical rays from the top of the box to "
+                        f"the 0.1 isosurface ({int(ok.sum())} of {n} hit), 16 points each at spacing {h:g}",
+            "bbox_diagonal": diag, "points": int(len(Ps)), "switch_points": int(sw.sum()),
+            "value_discrepancy_mean": float(dd.mean()) if dd.size else None,
+            "value_discrepancy_max": float(dd.max()) if dd.size else None,
+            "gradient_cosine_mean": float(cos.mean()) if cos.size else None,
+            "gradient_cosine_min": float(cos.min()) if cos.size else None}
 
 
 def sweep_leg(args, np, torch, api, scenes):

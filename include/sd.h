@@ -194,6 +194,24 @@ int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64_t K,
                      float *Rbar, float *tbar, float *Xbar, void *stream);
 
 /*
+ * Sphere tracing of the level set d = level of the smooth distance (Sec. 4.2
+ * renders the zero isosurface this way; Hart 1996): for each ray i with
+ * origin O_i and unit direction U_i (n x 3 each), x = O_i + t U_i starts at
+ * t = 0 and advances by r = d(x) - level (Eq. 3 through Alg. 1 / Alg. 2 with
+ * the parameters p, value only) until r <= eps: t_out[i] = t (a hit);
+ * t > t_max, max_steps evaluations or a NaN distance: t_out[i] = +inf.
+ * steps_out (may be NULL) receives the number of evaluations per ray.  A step
+ * of r is safe where d is 1-Lipschitz (point clouds; the blended weights of
+ * edges and triangles can raise |grad d| slightly above 1).  All arrays are
+ * device memory; the march runs inside one kernel.
+ * Errors: SD_EINVAL for a null scene or pointers, n < 0, bad p (as sd_eval),
+ * eps <= 0, t_max < 0, a non-finite level or max_steps < 1.
+ */
+int sd_sphere_trace(const sd_scene *scene, const float *O, const float *U, int64_t n,
+                    const sd_params *p, float level, float eps, float t_max, int32_t max_steps,
+                    float *t_out, int32_t *steps_out, void *stream);
+
+/*
  * Smooth distance between the data mesh and a query mesh (Sec. 3.6), for K
  * instances of one query mesh (e.g. K rigid placements of a body): from the
  * per-primitive smooth distances d (K x m, row k = instance k, as computed by

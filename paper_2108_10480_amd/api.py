@@ -51,7 +51,7 @@ _lib = None
 EXPORTED = ["sd_build_bvh", "sd_free_scene", "sd_scene_info_get", "sd_eval", "sd_eval_grad",
             "sd_eval_brute", "sd_eval_counters", "sd_export_bvh", "sd_export_weights",
             "sd_query_order", "sd_eval_grad_ordered",
-            "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint", "sd_query_mesh_lse",
+            "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint", "sd_query_mesh_lse", "sd_sphere_trace",
             "sd_surrogate_create", "sd_surrogate_free", "sd_surrogate_forward",
             "sd_surrogate_loss_grad", "sd_surrogate_adam", "sd_surrogate_train_step",
             "sd_surrogate_certify", "sd_surrogate_certify_cells", "sd_surrogate_save", "sd_surrogate_load", "sd_eval_surrogate",
@@ -294,6 +294,23 @@ class RigidSmoothDistance(torch.autograd.Function):
 
 def rigid_smooth_distance(X, R, t, scene, alpha, beta=0.5, alpha_u=0.0, flags=0):
     return RigidSmoothDistance.apply(X, R, t, scene, alpha, beta, alpha_u, flags)
+
+
+def sd_sphere_trace(scene, O, U, alpha, beta=0.5, alpha_u=0.0, flags=0, level=0.0, eps=1e-4, t_max=10.0,
+                    max_steps=256, want_steps=True):
+    """Sphere tracing of the level set d = level along rays (O, U) (n x 3
+    each, U unit): (t (n,) with +inf for a miss, steps (n,) int32 or None)."""
+    Op, n = _dptr(O, torch.float32, "O", 3)
+    Up, n2 = _dptr(U, torch.float32, "U", 3)
+    if n2 != n:
+        raise ValueError("O and U must have the same number of rays")
+    p = params(alpha, beta, alpha_u, flags)
+    t = torch.empty(n, dtype=torch.float32, device=O.device)
+    st = torch.empty(n, dtype=torch.int32, device=O.device) if want_steps else None
+    _check(lib().sd_sphere_trace(scene.handle, Op, Up, _i64(n), ctypes.byref(p), ctypes.c_float(level),
+                                 ctypes.c_float(eps), ctypes.c_float(t_max), ctypes.c_int32(max_steps),
+                                 _c_p(t.data_ptr()), _c_p(st.data_ptr() if st is not None else 0), _stream()))
+    return t, st
 
 
 def sd_query_mesh_lse(d, grad, alpha_q, prim=None, nV=None, want_w=True, want_vgrad=True):

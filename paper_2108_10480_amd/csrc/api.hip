@@ -113,6 +113,19 @@ int sd_eval(const sd_scene *sc, const float *Q, int64_t nQ, const sd_params *p, 
     return sd::eval_dispatch(sc, Q, nullptr, nQ, p, d_out, nullptr, nullptr, false, (hipStream_t)stream);
 }
 
+int sd_sphere_trace(const sd_scene *sc, const float *O, const float *U, int64_t n, const sd_params *p,
+                    float level, float eps, float t_max, int32_t max_steps, float *t_out, int32_t *steps_out,
+                    void *stream) {
+    if (!sc) return sd::fail(SD_EINVAL, "sd_sphere_trace: null scene");
+    if (n < 0) return sd::fail(SD_EINVAL, "sd_sphere_trace: negative ray count");
+    SD_TRY(sd::check_params(p, "sd_sphere_trace"));
+    if (!(eps > 0.f) || !isfinite(eps) || !(t_max >= 0.f) || !isfinite(level) || max_steps < 1)
+        return sd::fail(SD_EINVAL, "sd_sphere_trace: need eps > 0, t_max >= 0, finite level, max_steps >= 1");
+    if (n > 0 && (!O || !U || !t_out)) return sd::fail(SD_EINVAL, "sd_sphere_trace: null pointer");
+    return sd::trace_dispatch(sc, O, U, n, p, level, eps, t_max, max_steps, t_out, steps_out,
+                              (hipStream_t)stream);
+}
+
 int sd_eval_grad(const sd_scene *sc, const float *Q, int64_t nQ, const sd_params *p, float *d_out,
                  float *grad_out, void *stream) {
     SD_TRY(sd::check_eval(sc, Q, nQ, p, d_out, "sd_eval_grad"));

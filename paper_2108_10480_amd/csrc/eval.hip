@@ -461,9 +461,9 @@ __device__ __forceinline__ void wave_sync() {
 template <int CLS, bool GRAD, bool COUNT, bool PRUNE>
 __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, float qx, float qy,
                                          float qz, LSE &st, int &n_vis, int &n_far, int &n_leaf,
-                                         LeafQueue &lq) {
+                                         LeafQueue &lq, bool active = true) {
     const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
-    int node = T.n_nodes > 0 ? 0 : -1;
+    int node = (active && T.n_nodes > 0) ? 0 : -1;
     float4 leaf_lo = make_float4(0.f, 0.f, 0.f, 0.f);
     if (node >= 0 && st.s == 0.0 && st.dref == INFINITY) {
         float sd = seed_distance(T, qx, qy, qz, A.inv_alpha);
@@ -580,9 +580,10 @@ __device__ __forceinline__ int xcd_block(int i, int G) {
 }
 
 template <bool GRAD>
-__device__ __forceinline__ void finalize(const EvalArgs &A, const LSE &st, int qi) {
+__device__ __forceinline__ void final_value(const EvalArgs &A, const LSE &st, float &d, float &gx,
+                                            float &gy, float &gz) {
     float sum = (float)st.s;
-    float d, gx = 0.f, gy = 0.f, gz = 0.f;
+    gx = gy = gz = 0.f;
     if (!(sum > 0.f) && !(sum != sum)) {
         d = INFINITY;   // empty scene: the empty sum
     } else {
@@ -608,6 +609,12 @@ __device__ __forceinline__ void finalize(const EvalArgs &A, const LSE &st, int q
             gz = (float)st.gz * inv;
         }
     }
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void finalize(const EvalArgs &A, const LSE &st, int qi) {
+    float d, gx, gy, gz;
+    final_value<GRAD>(A, st, d, gx, gy, gz);
     A.d_out[qi] = d;
     if (GRAD) {
         A.g_out[3 * (int64_t)qi] = gx;
@@ -723,6 +730,68 @@ k_query_keys(const float *__restrict__ Q, const uint32_t *__restrict__ idx, int6
     vals[i] = (uint32_t)j;
 }
 
+// Sphere tracing of the level set d = level (Hart 1996; Sec. 4.2 renders the
+// zero isosurface this way): per ray, x = o + t u starts at t = 0 and moves by
+// r = d(x) - level until r <= eps (hit at t), t > t_max or max_steps steps
+// (miss: +inf).  Each step is one full Alg. 1 / Alg. 2 evaluation (value only)
+// inside this kernel; a lane whose ray has ended leaves the loop, and the
+// traversal's wave-cooperative leaf stage works with the lanes still present.
+struct TraceArgs {
+    const float *O, *U;
+    float level, eps, t_max;
+    int32_t max_steps;
+    float *t_out;
+    int32_t *steps_out;
+};
+
+template <int MASK>
+__global__ void __launch_bounds__(kB) k_trace(EvalArgs A, TraceArgs R) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= A.nq) return;
+    const float ox = R.O[3 * (int64_t)i], oy = R.O[3 * (int64_t)i + 1], oz = R.O[3 * (int64_t)i + 2];
+    const float ux = R.U[3 * (int64_t)i], uy = R.U[3 * (int64_t)i + 1], uz = R.U[3 * (int64_t)i + 2];
+    __shared__ LeafQueue lqs[(MASK & 6) ? kB / 64 : 1];
+    LeafQueue &lq = lqs[(MASK & 6) ? threadIdx.x / 64 : 0];
+    float t = 0.f, t_hit = INFINITY;
+    int steps = 0;
+    while (true) {
+        const float qx = fmaf(t, ux, ox), qy = fmaf(t, uy, oy), qz = fmaf(t, uz, oz);
+        LSE st;
+        lse_init(st);
+        int nv = 0, nf = 0, nl = 0;
+        if (MASK & 1) traverse<0, false, false, false>(A.tree[0], A, qx, qy, qz, st, nv, nf, nl, lq);
+        if (MASK & 2) traverse<1, false, false, false>(A.tree[1], A, qx, qy, qz, st, nv, nf, nl, lq);
+        if (MASK & 4) traverse<2, false, false, false>(A.tree[2], A, qx, qy, qz, st, nv, nf, nl, lq);
+        float d, gx, gy, gz;
+        final_value<false>(A, st, d, gx, gy, gz);
+        ++steps;
+        const float r = d - R.level;
+        if (r <= R.eps) {
+            t_hit = t;
+            break;
+        }
+        t += r;
+        if (!(t <= R.t_max) || steps >= R.max_steps) break;   // also ends NaN rays
+    }
+    R.t_out[i] = t_hit;
+    if (R.steps_out) R.steps_out[i] = steps;
+}
+
+void launch_trace(const EvalArgs &A, const TraceArgs &R, int mask, unsigned grid, hipStream_t s) {
+    switch (mask & 7) {
+#define SD_CASE(m) \
+    case m: hipLaunchKernelGGL((k_trace<m>), dim3(grid), dim3(kB), 0, s, A, R); break;
+        SD_CASE(1) SD_CASE(2) SD_CASE(3) SD_CASE(4) SD_CASE(5) SD_CASE(6) SD_CASE(7)
+#undef SD_CASE
+        default: break;
+    }
+}
+
+__global__ void __launch_bounds__(kB) k_fill_f32(float *__restrict__ p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 template <bool GRAD, bool COUNT>
 void launch_eval(const EvalArgs &A, int mask, unsigned grid, hipStream_t s) {
     switch (mask) {
@@ -775,15 +844,10 @@ static int defer_threshold() {
     return v;
 }
 
-int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, int64_t nq,
-                  const sd_params *p, float *d_out, float *g_out, int32_t *counts, bool brute,
-                  hipStream_t s, int64_t nthr) {
-    if (nthr < 0) nthr = nq;
-    if (nq == 0 || nthr == 0) return SD_OK;
-    if (nq > (int64_t)0x7fffffff - kB) return fail(SD_EUNSUPPORTED, "more than 2^31 queries per call");
-    if (nthr != nq && (!perm_in || brute || counts || nthr > nq))
-        return fail(SD_EINVAL, "a thread count below the query count needs an index list");
-    EvalArgs A;
+// Arguments common to every evaluation (per-class hierarchies, weight data,
+// alpha, beta, flags); returns the kernel variant: class mask (bits 1, 2, 4)
+// plus 8 when negligible subtrees are skipped.
+static int make_args(const sd_scene *sc, const sd_params *p, EvalArgs &A) {
     memset(&A, 0, sizeof(A));
     double alpha = p->alpha;
     double S = alpha / std::max<double>(alpha, p->alpha_u);
@@ -815,14 +879,7 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
     A.defer = defer_threshold();
     A.prune = 64.f;
     A.flags = p->flags;
-    A.nq = (int32_t)nq;
-    A.nthr = (int32_t)nthr;
-    A.Q = Q;
-    A.d_out = d_out;
-    A.g_out = g_out;
-    A.counts = counts;
     int mask = (sc->n[0] > 0 ? 1 : 0) | (sc->n[1] > 0 ? 2 : 0) | (sc->n[2] > 0 ? 4 : 0);
-    unsigned grid = (unsigned)((nthr + kB - 1) / kB);
     // Negligible-subtree skipping (bit 8 of the kernel variant) only where it
     // can pay for its per-node test: a subtree is skipped when it lies at
     // least 64/alpha beyond the running reference, which inside a scene of
@@ -832,6 +889,26 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
         double diag = sqrt(ex * ex + ey * ey + ez * ez);
         if (mask != 0 && !(p->flags & SD_NO_PRUNE) && alpha * diag > 1000.0) mask |= 8;
     }
+    return mask;
+}
+
+int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, int64_t nq,
+                  const sd_params *p, float *d_out, float *g_out, int32_t *counts, bool brute,
+                  hipStream_t s, int64_t nthr) {
+    if (nthr < 0) nthr = nq;
+    if (nq == 0 || nthr == 0) return SD_OK;
+    if (nq > (int64_t)0x7fffffff - kB) return fail(SD_EUNSUPPORTED, "more than 2^31 queries per call");
+    if (nthr != nq && (!perm_in || brute || counts || nthr > nq))
+        return fail(SD_EINVAL, "a thread count below the query count needs an index list");
+    EvalArgs A;
+    int mask = make_args(sc, p, A);
+    A.nq = (int32_t)nq;
+    A.nthr = (int32_t)nthr;
+    A.Q = Q;
+    A.d_out = d_out;
+    A.g_out = g_out;
+    A.counts = counts;
+    unsigned grid = (unsigned)((nthr + kB - 1) / kB);
 
     if (mask == 0) {
         // empty scene: the empty sum gives +inf and a zero gradient
@@ -867,6 +944,28 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
     }
     SD_HIP(hipGetLastError());
     if (perm) SD_HIP(hipFreeAsync(perm, s));
+    return SD_OK;
+}
+
+int trace_dispatch(const sd_scene *sc, const float *O, const float *U, int64_t n, const sd_params *p,
+                   float level, float eps, float t_max, int32_t max_steps, float *t_out, int32_t *steps_out,
+                   hipStream_t s) {
+    if (n == 0) return SD_OK;
+    if (n > (int64_t)0x7fffffff - kB) return fail(SD_EUNSUPPORTED, "more than 2^31 rays per call");
+    EvalArgs A;
+    const int mask = make_args(sc, p, A) & 7;   // value only, no subtree skipping
+    A.nq = (int32_t)n;
+    A.nthr = (int32_t)n;
+    const unsigned grid = (unsigned)((n + kB - 1) / kB);
+    if (mask == 0) {   // empty scene: d = +inf everywhere, every ray misses
+        hipLaunchKernelGGL(k_fill_f32, dim3(grid), dim3(kB), 0, s, t_out, n, INFINITY);
+        if (steps_out) SD_HIP(hipMemsetAsync(steps_out, 0, n * sizeof(int32_t), s));
+        SD_HIP(hipGetLastError());
+        return SD_OK;
+    }
+    TraceArgs R{O, U, level, eps, t_max, max_steps, t_out, steps_out};
+    launch_trace(A, R, mask, grid, s);
+    SD_HIP(hipGetLastError());
     return SD_OK;
 }
 
