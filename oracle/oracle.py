@@ -12,7 +12,8 @@ What lives here (each function cites the passage it follows):
 * triangle weight polynomial (pseudoinverse) .... App. C.3
 * global weight scale A per class ............... Sec. 3.3, App. C.2, App. C.3
 * brute-force and Barnes-Hut evaluation ......... Eq. 3, Eq. 4, Alg. 1, Alg. 2
-  (in C, see sd_oracle.c)
+  (in C, see sd_oracle.c); edges and triangles as query primitives (Sec. 3.4)
+  with the simplex-simplex distances of App. B
 * the surrogate network in FP64 (forward, backward, input gradient, Adam):
   see ``mlp.py``
 
@@ -401,6 +402,56 @@ def barnes_hut(scene: OracleScene, trees, Q, alpha, beta, alpha_u=0.0, metric_r2
     if rc != 0:
         raise ValueError("oracle barnes_hut: bad parameters")
     return d, g, st
+
+
+def _prims(G):
+    G = np.ascontiguousarray(G, np.float64)
+    if G.ndim != 3 or G.shape[2] != 3 or not 1 <= G.shape[1] <= 3:
+        raise ValueError("query primitives must be (n, nv, 3) with nv in 1..3")
+    return G, G.shape[0], G.shape[1]
+
+
+def brute_prims(scene: OracleScene, G, alpha, alpha_u=0.0, metric_r2=False):
+    """Eq. 3 and Eq. 4 over every primitive for query primitives G (n, nv, 3):
+    nv = 1 points, 2 edges, 3 triangles (Sec. 3.4).  Returns (d, grad, d_min)."""
+    G, n, nv = _prims(G)
+    d, g, dm = np.empty(n), np.empty((n, 3)), np.empty(n)
+    s, p = scene._struct(), _params(alpha, alpha_u, 0.0, metric_r2)
+    rc = lib().or_brute_prims(ctypes.byref(s), ctypes.byref(p), ctypes.c_int64(n), _ptr(G), ctypes.c_int(nv),
+                              _ptr(d), _ptr(g), _ptr(dm))
+    if rc != 0:
+        raise ValueError("oracle brute_prims: bad parameters")
+    return d, g, dm
+
+
+def barnes_hut_prims(scene: OracleScene, trees, G, alpha, beta, alpha_u=0.0, metric_r2=False, cut_f32=False):
+    """Alg. 1 + Alg. 2 for query primitives G (n, nv, 3) with the box distance
+    from the per-axis gaps of the halfspaces g lies outside of (App. D for
+    general primitives); stats as in barnes_hut."""
+    G, n, nv = _prims(G)
+    arr = (_OrTree * 3)()
+    for c in range(3):
+        if trees[c] is None:
+            arr[c].n_nodes = 0
+        else:
+            arr[c] = trees[c]._struct()
+    d, g, st = np.empty(n), np.empty((n, 3)), np.empty((n, 4))
+    s, p = scene._struct(), _params(alpha, alpha_u, beta, metric_r2, cut_f32)
+    rc = lib().or_barnes_hut_prims(ctypes.byref(s), ctypes.byref(p), arr, ctypes.c_int64(n), _ptr(G),
+                                   ctypes.c_int(nv), _ptr(d), _ptr(g), _ptr(st))
+    if rc != 0:
+        raise ValueError("oracle barnes_hut_prims: bad parameters")
+    return d, g, st
+
+
+def simplex_distance(A, B):
+    """Distance between two simplices (1-3 vertices each, rows xyz) and the
+    closest point on B (App. B, Eq. 10)."""
+    A = np.ascontiguousarray(A, np.float64).reshape(-1, 3)
+    B = np.ascontiguousarray(B, np.float64).reshape(-1, 3)
+    out = np.empty(4)
+    lib().or_simplex_distance(_ptr(A), ctypes.c_int(len(A)), _ptr(B), ctypes.c_int(len(B)), _ptr(out))
+    return out[0], out[1:]
 
 
 def rigid_apply(X, R, t):

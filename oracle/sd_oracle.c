@@ -433,6 +433,299 @@ int or_barnes_hut(const or_scene *sc, const or_params *p, const or_tree *trees,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Sec. 3.4: edges and triangles as query primitives                        */
+/* ------------------------------------------------------------------------ */
+/* A query primitive g has nv = 1, 2 or 3 vertices.  d(f_i, g) is the convex
+ * QP of App. B over both simplices (Eq. 10); its minimiser gives the closest
+ * point g(lambda) on g.  Sec. 3.4 then evaluates every formula of the point
+ * query with q replaced by g(lambda): the distance from g(lambda) to f_i is
+ * d(f_i, g), the weight uses the closest point on f_i, and the gradient is
+ * the point-query gradient at g(lambda) (a rigid translation of g).
+ *
+ * The QP minimum of two convex simplices is found by enumeration: either the
+ * two intersect (distance 0) or a closest pair has a point on a boundary
+ * feature of one of them, so the candidates are the vertex-simplex and
+ * edge-edge pairs (plus the interior edge-edge solution), each solved in
+ * closed form below. */
+
+/* closest points of segments p0 p1 and q0 q1: returns |x - y| and the point y
+ * on the second segment */
+static double segseg(v3 p0, v3 p1, v3 q0, v3 q1, v3 *y_out) {
+    v3 u = sub(p1, p0), v = sub(q1, q0), w = sub(p0, q0);
+    double a = dot(u, u), b = dot(u, v), c = dot(v, v), d = dot(u, w), e = dot(v, w);
+    double best = INFINITY;
+    v3 by = q0;
+    double den = a * c - b * b;
+    if (a > 0 && c > 0 && den > 1e-300 * a * c) {          /* interior stationary point */
+        double s = (b * e - c * d) / den, t = (a * e - b * d) / den;
+        if (s >= 0 && s <= 1 && t >= 0 && t <= 1) {
+            v3 x = add(p0, scl(u, s)), y = add(q0, scl(v, t));
+            best = norm(sub(x, y)); by = y;
+        }
+    }
+    /* boundary: an endpoint of one segment against the other segment */
+    closest cp;
+    segment_closest(p0, q0, q1, &cp); if (cp.d < best) { best = cp.d; by = cp.c; }
+    segment_closest(p1, q0, q1, &cp); if (cp.d < best) { best = cp.d; by = cp.c; }
+    segment_closest(q0, p0, p1, &cp); if (cp.d < best) { best = cp.d; by = q0; }
+    segment_closest(q1, p0, p1, &cp); if (cp.d < best) { best = cp.d; by = q1; }
+    *y_out = by;
+    return best;
+}
+
+/* does segment p0 p1 cross triangle t0 t1 t2?  returns 1 and the crossing point */
+static int seg_tri_cross(v3 p0, v3 p1, v3 t0, v3 t1, v3 t2, v3 *x) {
+    v3 n = cross(sub(t1, t0), sub(t2, t0));
+    double nn = dot(n, n);
+    if (!(nn > 0)) return 0;
+    double s0 = dot(n, sub(p0, t0)), s1 = dot(n, sub(p1, t0));
+    if ((s0 > 0 && s1 > 0) || (s0 < 0 && s1 < 0) || s0 == s1) return 0;
+    double a = s0 / (s0 - s1);
+    v3 y = add(p0, scl(sub(p1, p0), a));
+    closest cp;
+    triangle_closest(y, t0, t1, t2, &cp);
+    if (cp.d > 1e-12 * (1 + norm(y))) return 0;
+    *x = y;
+    return 1;
+}
+
+/* segment p0 p1 against triangle t0 t1 t2: distance, the closest point on the
+ * segment (*xs) and on the triangle (*xt) */
+static double segtri(v3 p0, v3 p1, v3 t0, v3 t1, v3 t2, v3 *xs, v3 *xt) {
+    v3 x;
+    if (seg_tri_cross(p0, p1, t0, t1, t2, &x)) { *xs = x; *xt = x; return 0.0; }
+    double best = INFINITY;
+    closest cp;
+    triangle_closest(p0, t0, t1, t2, &cp); if (cp.d < best) { best = cp.d; *xs = p0; *xt = cp.c; }
+    triangle_closest(p1, t0, t1, t2, &cp); if (cp.d < best) { best = cp.d; *xs = p1; *xt = cp.c; }
+    v3 T[3] = {t0, t1, t2};
+    for (int k = 0; k < 3; ++k) {
+        v3 y, xx;
+        double d = segseg(T[k], T[(k + 1) % 3], p0, p1, &xx);   /* xx on p0 p1 */
+        if (d < best) {
+            best = d; *xs = xx;
+            segment_closest(xx, T[k], T[(k + 1) % 3], &cp); *xt = cp.c;
+        }
+        (void)y;
+    }
+    return best;
+}
+
+/* closest point on the query primitive g (nv vertices) to data primitive
+ * (class cls, index i) */
+static v3 closest_on_query(const or_scene *sc, int cls, int64_t i, const v3 *g, int nv) {
+    closest cp;
+    if (nv == 1) return g[0];
+    if (cls == 0) {
+        v3 p = ld(sc->P + 3 * i);
+        if (nv == 2) segment_closest(p, g[0], g[1], &cp);
+        else triangle_closest(p, g[0], g[1], g[2], &cp);
+        return cp.c;
+    }
+    if (cls == 1) {
+        v3 a = ld(sc->E + 6 * i), b = ld(sc->E + 6 * i + 3), y, xs, xt;
+        if (nv == 2) { segseg(a, b, g[0], g[1], &y); return y; }
+        segtri(a, b, g[0], g[1], g[2], &xs, &xt);
+        return xt;                                   /* point on the query triangle */
+    }
+    const float *t = sc->T + 9 * i;
+    v3 t0 = ld(t), t1 = ld(t + 3), t2 = ld(t + 6), xs, xt;
+    if (nv == 2) { segtri(g[0], g[1], t0, t1, t2, &xs, &xt); return xs; }
+    /* triangle against triangle: a crossing edge gives distance 0; otherwise
+     * the closest pair involves an edge of one of them */
+    double best = INFINITY;
+    v3 out = g[0];
+    v3 G3[3] = {g[0], g[1], g[2]}, F3[3] = {t0, t1, t2};
+    for (int k = 0; k < 3; ++k) {
+        double d = segtri(G3[k], G3[(k + 1) % 3], t0, t1, t2, &xs, &xt);   /* xs on g */
+        if (d < best) { best = d; out = xs; }
+    }
+    for (int k = 0; k < 3; ++k) {
+        double d = segtri(F3[k], F3[(k + 1) % 3], g[0], g[1], g[2], &xs, &xt);   /* xt on g */
+        if (d < best) { best = d; out = xt; }
+    }
+    return out;
+}
+
+static int load_query(const double *G, int nv, int64_t k, v3 *g) {
+    for (int a = 0; a < nv; ++a) g[a] = ldd(G + 3 * (nv * k + a));
+    return nv;
+}
+
+/* exact smooth distance for general query primitives (beta = 0 semantics) */
+int or_brute_prims(const or_scene *sc, const or_params *p, int64_t nq, const double *G, int nv,
+                   double *d_out, double *g_out, double *dmin_out) {
+    if (!(p->alpha > 0) || nv < 1 || nv > 3) return -1;
+#pragma omp parallel
+    {
+        termlist tl = {0, 0, 0};
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t k = 0; k < nq; ++k) {
+            v3 g[3];
+            load_query(G, nv, k, g);
+            double dmin = INFINITY;
+            tl.n = 0;
+            for (int64_t i = 0; i < sc->nP; ++i) exact_term(sc, p, 0, i, closest_on_query(sc, 0, i, g, nv), &tl, &dmin);
+            for (int64_t i = 0; i < sc->nE; ++i) exact_term(sc, p, 1, i, closest_on_query(sc, 1, i, g, nv), &tl, &dmin);
+            for (int64_t i = 0; i < sc->nT; ++i) exact_term(sc, p, 2, i, closest_on_query(sc, 2, i, g, nv), &tl, &dmin);
+            lse_finish(&tl, p->alpha, d_out + k, g_out + 3 * k);
+            if (dmin_out) dmin_out[k] = dmin;
+        }
+        free(tl.t);
+    }
+    return 0;
+}
+
+/* App. D for a general query primitive: the box is the intersection of six
+ * halfspaces; along each axis g lies entirely above the box (min over its
+ * vertices beyond max), entirely below, or neither.  The per-axis gaps
+ * delta_a (signed, 0 for "neither") give D = |delta|, a lower bound of the
+ * distance between the box and g (exact for a point, where delta = q - y_B),
+ * and the far-field direction delta / D.  No outside halfspace: D = 0 and the
+ * node is opened.  With cut_f32 the gaps, D^2 and the test are formed in FP32
+ * as for points. */
+static v3 query_gap(const float *b, const v3 *g, int nv) {
+    double gp[3];
+    for (int a = 0; a < 3; ++a) {
+        double mn = INFINITY, mx = -INFINITY;
+        for (int v = 0; v < nv; ++v) {
+            double c = a == 0 ? g[v].x : (a == 1 ? g[v].y : g[v].z);
+            if (c < mn) mn = c;
+            if (c > mx) mx = c;
+        }
+        gp[a] = mn > b[3 + a] ? mn - b[3 + a] : (mx < b[a] ? mx - b[a] : 0.0);
+    }
+    return mk(gp[0], gp[1], gp[2]);
+}
+
+static int accept_far_query(const or_params *p, const float *b, const v3 *g, int nv, double D, double diam) {
+    if (!p->cut_f32) return diam < p->beta * D;
+    float gp[3];
+    for (int a = 0; a < 3; ++a) {
+        float mn = INFINITY, mx = -INFINITY;
+        for (int v = 0; v < nv; ++v) {
+            float c = (float)(a == 0 ? g[v].x : (a == 1 ? g[v].y : g[v].z));
+            mn = fminf(mn, c);
+            mx = fmaxf(mx, c);
+        }
+        gp[a] = mn > b[3 + a] ? mn - b[3 + a] : (mx < b[a] ? mx - b[a] : 0.0f);
+    }
+    float D2 = fmaf(gp[0], gp[0], fmaf(gp[1], gp[1], gp[2] * gp[2]));
+    float ex = b[3] - b[0], ey = b[4] - b[1], ez = b[5] - b[2];
+    float B2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+    float bf = (float)p->beta;
+    return B2 < (bf * bf) * D2;
+}
+
+typedef struct {
+    const or_scene *sc; const or_params *p; const v3 *g; int nv; int cls;
+    const or_tree *tr; const int64_t *nleaf; double logA;
+    termlist *tl; double margin; int64_t visited, far, leaves;
+} bhq_ctx;
+
+static void collect_q(bhq_ctx *cx, int32_t node) {
+    const float *b = cx->tr->box + 6 * (int64_t)node;
+    v3 lo = ld(b), hi = ld(b + 3);
+    v3 gap = query_gap(b, cx->g, cx->nv);
+    double D = norm(gap);
+    double diam = norm(sub(hi, lo));
+    cx->visited++;
+    if (D > 0) {
+        double m = fabs(cx->p->beta * D - diam) / D;
+        if (m < cx->margin) cx->margin = m;
+    }
+    if (accept_far_query(cx->p, b, cx->g, cx->nv, D, diam)) {
+        double logW = log((double)cx->nleaf[node]) + atten(cx->p) * cx->logA;
+        push(cx->tl, logW - cx->p->alpha * D, scl(gap, 1.0 / D));
+        cx->far++;
+        return;
+    }
+    if (cx->tr->left[node] < 0) {
+        double dm = INFINITY;
+        int64_t i = cx->tr->prim[node];
+        exact_term(cx->sc, cx->p, cx->cls, i, closest_on_query(cx->sc, cx->cls, i, cx->g, cx->nv), cx->tl, &dm);
+        cx->leaves++;
+        return;
+    }
+    collect_q(cx, cx->tr->left[node]);
+    collect_q(cx, cx->tr->right[node]);
+}
+
+int or_barnes_hut_prims(const or_scene *sc, const or_params *p, const or_tree *trees, int64_t nq,
+                        const double *G, int nv, double *d_out, double *g_out, double *stats) {
+    if (!(p->alpha > 0) || !(p->beta >= 0) || nv < 1 || nv > 3) return -1;
+    int64_t *nleaf[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+        if (trees[c].n_nodes <= 0) continue;
+        nleaf[c] = (int64_t *)calloc((size_t)trees[c].n_nodes, sizeof(int64_t));
+        count_leaves(&trees[c], 0, nleaf[c]);
+    }
+    double logA[3] = {0.0, sc->logA_E, sc->logA_T};
+#pragma omp parallel
+    {
+        termlist tl = {0, 0, 0};
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t k = 0; k < nq; ++k) {
+            v3 g[3];
+            load_query(G, nv, k, g);
+            tl.n = 0;
+            bhq_ctx cx;
+            memset(&cx, 0, sizeof cx);
+            cx.sc = sc; cx.p = p; cx.g = g; cx.nv = nv; cx.tl = &tl; cx.margin = INFINITY;
+            for (int c = 0; c < 3; ++c) {
+                if (trees[c].n_nodes <= 0) continue;
+                cx.cls = c; cx.tr = &trees[c]; cx.nleaf = nleaf[c]; cx.logA = logA[c];
+                collect_q(&cx, 0);
+            }
+            lse_finish(&tl, p->alpha, d_out + k, g_out + 3 * k);
+            if (stats) {
+                stats[4 * k + 0] = cx.margin; stats[4 * k + 1] = (double)cx.visited;
+                stats[4 * k + 2] = (double)cx.far; stats[4 * k + 3] = (double)cx.leaves;
+            }
+        }
+        free(tl.t);
+    }
+    for (int c = 0; c < 3; ++c) free(nleaf[c]);
+    return 0;
+}
+
+/* the closest pair of two simplices (for the pins): distance and the point
+ * on the second; nva, nvb in 1..3 vertices, A and B as xyz rows */
+int or_simplex_distance(const double *A, int nva, const double *B, int nvb, double *out) {
+    v3 a[3], b[3];
+    for (int k = 0; k < nva; ++k) a[k] = ldd(A + 3 * k);
+    for (int k = 0; k < nvb; ++k) b[k] = ldd(B + 3 * k);
+    v3 y = b[0], xs, xt;
+    double d;
+    closest cp;
+    if (nva == 1) {
+        if (nvb == 1) { d = norm(sub(a[0], b[0])); y = b[0]; }
+        else if (nvb == 2) { segment_closest(a[0], b[0], b[1], &cp); d = cp.d; y = cp.c; }
+        else { triangle_closest(a[0], b[0], b[1], b[2], &cp); d = cp.d; y = cp.c; }
+    } else if (nva == 2) {
+        if (nvb == 1) { segment_closest(b[0], a[0], a[1], &cp); d = cp.d; y = b[0]; }
+        else if (nvb == 2) d = segseg(a[0], a[1], b[0], b[1], &y);
+        else { d = segtri(a[0], a[1], b[0], b[1], b[2], &xs, &xt); y = xt; }
+    } else {
+        if (nvb == 1) { triangle_closest(b[0], a[0], a[1], a[2], &cp); d = cp.d; y = b[0]; }
+        else if (nvb == 2) { d = segtri(b[0], b[1], a[0], a[1], a[2], &xs, &xt); y = xs; }
+        else {
+            d = INFINITY;
+            for (int k = 0; k < 3; ++k) {
+                double e = segtri(b[k], b[(k + 1) % 3], a[0], a[1], a[2], &xs, &xt);
+                if (e < d) { d = e; y = xs; }
+            }
+            for (int k = 0; k < 3; ++k) {
+                double e = segtri(a[k], a[(k + 1) % 3], b[0], b[1], b[2], &xs, &xt);
+                if (e < d) { d = e; y = xt; }
+            }
+        }
+    }
+    out[0] = d; out[1] = y.x; out[2] = y.y; out[3] = y.z;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Rigidly moved queries x' = R_k x_j + t_k and the adjoint of d(x')          */
 /* ------------------------------------------------------------------------ */
 /* X: m x 3, R: K x 9 row-major, t: K x 3  ->  Qout: (K*m) x 3 (double) */
