@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--beta-ablation", action="store_true",
                     help="sphere-trace renders of vertex, edge and triangle scenes over beta (Sec. 4.3 analogue)")
     ap.add_argument("--ablation-res", type=int, default=256, help="image side of the beta ablation renders")
+    ap.add_argument("--prims", action="store_true",
+                    help="edges and triangles as query primitives on the benchmark scene (Sec. 3.4)")
     ap.add_argument("--switch-study", action="store_true",
                     help="near/far switch discrepancy beta 0.5 vs 0.5001 on the street points (Sec. 4.3 analogue)")
     ap.add_argument("--sur-train", type=int, default=20_000_000, help="surrogate training samples")
@@ -277,6 +279,8 @@ def main():
         out["rigid"] = rigid_leg(args, np, torch, api, scenes)
     if args.sweep:
         out["precision_sweep"] = sweep_leg(args, np, torch, api, scenes)
+    if args.prims:
+        out["query_primitives"] = prims_leg(args, np, torch, api, scenes, sc, scene)
     if args.beta_ablation:
         out["beta_ablation"] = beta_ablation_leg(args, np, torch, api, scenes)
     if args.switch_study:
@@ -297,6 +301,50 @@ def _camera_rays(np, res, eye, fov_deg=40.0):
     D = f[None] + px.reshape(-1, 1) * r[None] + py.reshape(-1, 1) * u[None]
     D /= np.linalg.norm(D, axis=1, keepdims=True)
     return np.tile(eye, (len(D), 1)).astype(np.float32), D.astype(np.float32)
+
+
+def prims_leg(args, np, torch, api, scenes, sc, scene):
+    """Edges and triangles as query primitives (Sec. 3.4) on the benchmark
+    scene: 1M small random segments / triangles placed like the point queries
+    (half uniform in the box, half near the surface), alpha and beta as the
+    headline; throughput and an oracle sample."""
+    rng = np.random.default_rng(31)
+    n = 1_000_000
+    C = scenes.icosphere_queries(sc, n, seed_box=32, seed_surf=33)
+    out = {"workload": f"bumpy icosphere level {args.level} ({len(sc.T)} triangles), {n} query primitives "
+                       f"(random segments / triangles of size ~0.02 at the point-query positions), "
+                       f"alpha={args.alpha:g}, beta={args.beta:g}, value+gradient"}
+    for nv, name in ((2, "edges"), (3, "triangles")):
+        G = (C[:, None, :] + rng.normal(size=(n, nv, 3)) * 0.01).astype(np.float32)
+        Gd = torch.as_tensor(G, device="cuda")
+        api.sd_eval_grad_prims(scene, Gd, args.alpha, args.beta)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            d, g = api.sd_eval_grad_prims(scene, Gd, args.alpha, args.beta)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 3
+        row = {"ms": ms, "value": n / (ms * 1e-3), "unit": "query primitives/s"}
+        if not args.no_cpu_baseline:
+            from oracle import oracle as O
+            idx = np.sort(rng.choice(n, 2000, replace=False))
+            osc = O.OracleScene(sc.V, T=sc.T)
+            trees = [None, None, O.OracleTree(*api.sd_export_bvh(scene, 2))]
+            dn, _ = api.sd_eval_grad_prims(scene, Gd[torch.as_tensor(idx, device="cuda")], args.alpha, args.beta,
+                                           flags=api.SD_NO_CONSERVATIVE_ROUNDING)
+            dr, _, _ = O.barnes_hut_prims(osc, trees, G[idx].astype(np.float64), args.alpha, args.beta,
+                                          cut_f32=True)
+            _, _, dm = O.brute_prims(osc, G[idx[:200]].astype(np.float64), args.alpha)
+            floor = 1e-3 * float(np.linalg.norm(sc.V.max(0) - sc.V.min(0)))
+            e = O.value_error(dn.cpu().numpy(), dr, floor)
+            row["parity_sample"] = {"n": len(idx), "max_err_vs_oracle": float(e.max()),
+                                    "median_err_vs_oracle": float(np.median(e)),
+                                    "conservative_violations_of_200": int(np.sum(d[torch.as_tensor(idx[:200],
+                                                                           device="cuda")].cpu().numpy() > dm))}
+        out[name] = row
+    return out
 
 
 def beta_ablation_leg(args, np, torch, api, scenes):

@@ -194,6 +194,24 @@ int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64_t K,
                      float *Rbar, float *tbar, float *Xbar, void *stream);
 
 /*
+ * Value and gradient for query primitives that are edges or triangles
+ * (Sec. 3.4): G is n x nv x 3 (nv = 2: edges, 3: triangles; 1: points, the
+ * same as sd_eval_grad), device memory.  d(f_i, g) is the simplex-simplex
+ * distance of App. B (Eq. 10); each data primitive's term is the point-query
+ * term at the point g(lambda) of g closest to it (weights at the closest
+ * point on f_i), so grad_out is the derivative for a rigid translation of g
+ * in that reading.  Far-field boxes use the per-axis gaps of the box
+ * halfspaces that g lies outside of (App. D): a lower bound of the box
+ * distance (the far field stays conservative), equal to the point formula
+ * for a point; no such halfspace opens the node.  Intersecting primitives
+ * give distance 0 with the weight at one point of the intersection.
+ * Errors: SD_EINVAL for a null scene or pointers, n < 0, nv outside 1..3,
+ * bad p (as sd_eval).
+ */
+int sd_eval_grad_prims(const sd_scene *scene, const float *G, int32_t nv, int64_t n, const sd_params *p,
+                       float *d_out, float *grad_out, void *stream);
+
+/*
  * Sphere tracing of the level set d = level of the smooth distance (Sec. 4.2
  * renders the zero isosurface this way; Hart 1996): for each ray i with
  * origin O_i and unit direction U_i (n x 3 each), x = O_i + t U_i starts at

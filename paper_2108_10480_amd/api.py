@@ -51,7 +51,7 @@ _lib = None
 EXPORTED = ["sd_build_bvh", "sd_free_scene", "sd_scene_info_get", "sd_eval", "sd_eval_grad",
             "sd_eval_brute", "sd_eval_counters", "sd_export_bvh", "sd_export_weights",
             "sd_query_order", "sd_eval_grad_ordered",
-            "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint", "sd_query_mesh_lse", "sd_sphere_trace",
+            "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint", "sd_query_mesh_lse", "sd_sphere_trace", "sd_eval_grad_prims",
             "sd_surrogate_create", "sd_surrogate_free", "sd_surrogate_forward",
             "sd_surrogate_loss_grad", "sd_surrogate_adam", "sd_surrogate_train_step",
             "sd_surrogate_certify", "sd_surrogate_certify_cells", "sd_surrogate_save", "sd_surrogate_load", "sd_eval_surrogate",
@@ -294,6 +294,23 @@ class RigidSmoothDistance(torch.autograd.Function):
 
 def rigid_smooth_distance(X, R, t, scene, alpha, beta=0.5, alpha_u=0.0, flags=0):
     return RigidSmoothDistance.apply(X, R, t, scene, alpha, beta, alpha_u, flags)
+
+
+def sd_eval_grad_prims(scene, G, alpha, beta=0.5, alpha_u=0.0, flags=0):
+    """Value and gradient (rigid translation) for query primitives G (n, nv, 3):
+    nv = 2 edges, 3 triangles, 1 points (Sec. 3.4)."""
+    if not (isinstance(G, torch.Tensor) and G.is_cuda and G.dtype == torch.float32):
+        raise TypeError("G must be a float32 CUDA tensor")
+    if G.dim() != 3 or G.shape[2] != 3 or not 1 <= G.shape[1] <= 3:
+        raise ValueError("G must have shape (n, nv, 3) with nv in 1..3")
+    Gc = G.contiguous()
+    n, nv = Gc.shape[0], Gc.shape[1]
+    p = params(alpha, beta, alpha_u, flags)
+    d = torch.empty(n, dtype=torch.float32, device=G.device)
+    g = torch.empty((n, 3), dtype=torch.float32, device=G.device)
+    _check(lib().sd_eval_grad_prims(scene.handle, _c_p(Gc.data_ptr()), ctypes.c_int32(nv), _i64(n),
+                                    ctypes.byref(p), _c_p(d.data_ptr()), _c_p(g.data_ptr()), _stream()))
+    return d, g
 
 
 def sd_sphere_trace(scene, O, U, alpha, beta=0.5, alpha_u=0.0, flags=0, level=0.0, eps=1e-4, t_max=10.0,

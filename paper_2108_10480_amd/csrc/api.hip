@@ -113,6 +113,18 @@ int sd_eval(const sd_scene *sc, const float *Q, int64_t nQ, const sd_params *p, 
     return sd::eval_dispatch(sc, Q, nullptr, nQ, p, d_out, nullptr, nullptr, false, (hipStream_t)stream);
 }
 
+int sd_eval_grad_prims(const sd_scene *sc, const float *G, int32_t nv, int64_t n, const sd_params *p,
+                       float *d_out, float *grad_out, void *stream) {
+    if (!sc) return sd::fail(SD_EINVAL, "sd_eval_grad_prims: null scene");
+    if (n < 0) return sd::fail(SD_EINVAL, "sd_eval_grad_prims: negative count");
+    if (nv < 1 || nv > 3) return sd::fail(SD_EINVAL, "sd_eval_grad_prims: nv must be 1, 2 or 3");
+    SD_TRY(sd::check_params(p, "sd_eval_grad_prims"));
+    if (n > 0 && (!G || !d_out || !grad_out)) return sd::fail(SD_EINVAL, "sd_eval_grad_prims: null pointer");
+    if (nv == 1)   // a point: the point query
+        return sd::eval_dispatch(sc, G, nullptr, n, p, d_out, grad_out, nullptr, false, (hipStream_t)stream);
+    return sd::evalq_dispatch(sc, G, nv, n, p, d_out, grad_out, (hipStream_t)stream);
+}
+
 int sd_sphere_trace(const sd_scene *sc, const float *O, const float *U, int64_t n, const sd_params *p,
                     float level, float eps, float t_max, int32_t max_steps, float *t_out, int32_t *steps_out,
                     void *stream) {

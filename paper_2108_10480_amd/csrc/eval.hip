@@ -569,6 +569,339 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
     }
 }
 
+// ---------------------------------------------------------------------------
+// Edges and triangles as query primitives (Sec. 3.4).  A query primitive g
+// has NV = 2 or 3 vertices.  Each data primitive's term is the point-query
+// term at g(lambda), the point of g closest to it (the simplex-simplex QP of
+// App. B, Eq. 10, solved by enumerating its boundary candidates); far-field
+// boxes use the per-axis gaps of the halfspaces g lies outside of (App. D),
+// a lower bound of the box distance that equals the point formula for a
+// point, and direction gap / |gap|.
+// ---------------------------------------------------------------------------
+struct V3 {
+    float x, y, z;
+};
+__device__ __forceinline__ V3 v3m(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 vsub(V3 a, V3 b) { return v3m(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 vaxpy(V3 a, float s, V3 e) {   // a + s e
+    return v3m(fmaf(s, e.x, a.x), fmaf(s, e.y, a.y), fmaf(s, e.z, a.z));
+}
+__device__ __forceinline__ float vdot(V3 a, V3 b) { return dot3(a.x, a.y, a.z, b.x, b.y, b.z); }
+__device__ __forceinline__ V3 vcross(V3 a, V3 b) {
+    return v3m(dop(a.y, b.z, a.z, b.y), dop(a.z, b.x, a.x, b.z), dop(a.x, b.y, a.y, b.x));
+}
+__device__ __forceinline__ float vdist2(V3 a, V3 b) {
+    V3 d = vsub(a, b);
+    return vdot(d, d);
+}
+
+// closest point of segment a b to p
+__device__ __forceinline__ V3 seg_point(V3 p, V3 a, V3 b) {
+    V3 e = vsub(b, a);
+    float ee = vdot(e, e);
+    float t = ee > 0.f ? __builtin_amdgcn_fmed3f(fdiv(vdot(vsub(p, a), e), ee), 0.f, 1.f) : 0.f;
+    return vaxpy(a, t, e);
+}
+
+// closest point of triangle a b c to p: the plane projection when its
+// barycentrics are inside, else the closest of the three edges
+__device__ __forceinline__ V3 tri_point(V3 p, V3 a, V3 b, V3 c) {
+    V3 e1 = vsub(b, a), e2 = vsub(c, a), r = vsub(p, a);
+    float g11 = vdot(e1, e1), g12 = vdot(e1, e2), g22 = vdot(e2, e2);
+    float det = dop(g11, g22, g12, g12);
+    if (det > 1e-12f * g11 * g22) {
+        float r1 = vdot(e1, r), r2 = vdot(e2, r);
+        float inv = frcp(det);
+        float u = dop(g22, r1, g12, r2) * inv, v = dop(g11, r2, g12, r1) * inv;
+        if (u >= 0.f && v >= 0.f && u + v <= 1.f) return vaxpy(vaxpy(a, u, e1), v, e2);
+    }
+    V3 best = seg_point(p, a, b);
+    float bd = vdist2(p, best);
+    V3 y = seg_point(p, b, c);
+    float d = vdist2(p, y);
+    if (d < bd) { bd = d; best = y; }
+    y = seg_point(p, c, a);
+    d = vdist2(p, y);
+    if (d < bd) best = y;
+    return best;
+}
+
+// closest points of segments p0 p1 and q0 q1: squared distance, point on q
+__device__ __forceinline__ float seg_seg(V3 p0, V3 p1, V3 q0, V3 q1, V3 &on_q) {
+    V3 u = vsub(p1, p0), v = vsub(q1, q0), w = vsub(p0, q0);
+    float a = vdot(u, u), b = vdot(u, v), c = vdot(v, v), d = vdot(u, w), e = vdot(v, w);
+    float best = INFINITY;
+    float den = dop(a, c, b, b);
+    if (den > 1e-6f * a * c) {   // not (nearly) parallel: interior stationary point
+        float inv = frcp(den);
+        float s = dop(b, e, c, d) * inv, t = dop(a, e, b, d) * inv;
+        if (s >= 0.f && s <= 1.f && t >= 0.f && t <= 1.f) {
+            V3 x = vaxpy(p0, s, u), y = vaxpy(q0, t, v);
+            best = vdist2(x, y);
+            on_q = y;
+        }
+    }
+    V3 y = seg_point(p0, q0, q1);
+    float dd = vdist2(p0, y);
+    if (dd < best) { best = dd; on_q = y; }
+    y = seg_point(p1, q0, q1);
+    dd = vdist2(p1, y);
+    if (dd < best) { best = dd; on_q = y; }
+    dd = vdist2(q0, seg_point(q0, p0, p1));
+    if (dd < best) { best = dd; on_q = q0; }
+    dd = vdist2(q1, seg_point(q1, p0, p1));
+    if (dd < best) { best = dd; on_q = q1; }
+    return best;
+}
+
+// segment p0 p1 against triangle t0 t1 t2: squared distance, the closest point
+// on the segment (xs) and on the triangle (xt); a crossing gives 0
+__device__ __forceinline__ float seg_tri(V3 p0, V3 p1, V3 t0, V3 t1, V3 t2, V3 &xs, V3 &xt) {
+    V3 n = vcross(vsub(t1, t0), vsub(t2, t0));
+    float s0 = vdot(n, vsub(p0, t0)), s1 = vdot(n, vsub(p1, t0));
+    if ((s0 <= 0.f && s1 >= 0.f) || (s0 >= 0.f && s1 <= 0.f)) {
+        if (s0 != s1) {
+            V3 y = vaxpy(p0, s0 / (s0 - s1), vsub(p1, p0));
+            V3 z = tri_point(y, t0, t1, t2);
+            float tol = 1e-12f * (1.f + vdot(y, y));
+            if (vdist2(y, z) <= tol) {
+                xs = y;
+                xt = z;
+                return 0.f;
+            }
+        }
+    }
+    xs = p0;
+    xt = tri_point(p0, t0, t1, t2);
+    float best = vdist2(p0, xt);
+    V3 z = tri_point(p1, t0, t1, t2);
+    float d = vdist2(p1, z);
+    if (d < best) { best = d; xs = p1; xt = z; }
+    V3 T3[3] = {t0, t1, t2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        V3 y;
+        d = seg_seg(T3[k], T3[(k + 1) % 3], p0, p1, y);   // y on p0 p1
+        if (d < best) {
+            best = d;
+            xs = y;
+            xt = seg_point(y, T3[k], T3[(k + 1) % 3]);
+        }
+    }
+    return best;
+}
+
+template <int NV>
+struct QPrim {
+    V3 v[NV];
+    float mn[3], mx[3];   // per-axis extent of the vertices
+};
+
+// The point of the query primitive (vertices gv) closest to the data primitive
+// (vertices dv: 1 point, 2 edge, 3 triangle), all in one frame.
+template <int CLS, int NV>
+__device__ __forceinline__ V3 closest_on_query(const V3 (&dv)[3], const V3 (&gv)[NV]) {
+    V3 y, xs, xt;
+    if (CLS == 0) return NV == 2 ? seg_point(dv[0], gv[0], gv[1]) : tri_point(dv[0], gv[0], gv[1], gv[NV - 1]);
+    if (CLS == 1) {
+        if (NV == 2) {
+            seg_seg(dv[0], dv[1], gv[0], gv[1], y);
+            return y;
+        }
+        seg_tri(dv[0], dv[1], gv[0], gv[1], gv[NV - 1], xs, y);
+        return y;
+    }
+    if (NV == 2) {
+        seg_tri(gv[0], gv[1], dv[0], dv[1], dv[2], xs, xt);
+        return xs;
+    }
+    // triangle against triangle: the closest pair involves an edge of one of them
+    float best = INFINITY;
+    V3 out = gv[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float d = seg_tri(gv[k], gv[(k + 1) % NV], dv[0], dv[1], dv[2], xs, xt);
+        if (d < best) { best = d; out = xs; }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float d = seg_tri(dv[k], dv[(k + 1) % 3], gv[0], gv[1], gv[NV - 1], xs, xt);
+        if (d < best) { best = d; out = xt; }
+    }
+    return out;
+}
+
+// Leaf term for a query primitive: the point-query term at g(lambda).  Both
+// primitives are moved into the frame of the data primitive's first vertex
+// before anything is formed, so that g(lambda) carries rounding of the size
+// of the local offsets rather than of the absolute coordinates (the terms are
+// translation invariant; the weight data in .w is kept); the rounding of
+// g(lambda) adds 2^-20 |g(lambda)|_1 to the error bound.
+template <int CLS, bool GRAD, int NV>
+__device__ __forceinline__ Term leaf_term_q(const TreeView &T, const EvalArgs &A, int slot, float4 leaf_lo,
+                                            const QPrim<NV> &g, bool metric) {
+    float4 r[3];
+    if (CLS == 0) {
+        r[0] = leaf_lo;
+    } else if (CLS == 1) {
+        r[0] = T.leaf[2 * slot];
+        r[1] = T.leaf[2 * slot + 1];
+    } else {
+        r[0] = T.leaf[3 * slot];
+        r[1] = T.leaf[3 * slot + 1];
+        r[2] = T.leaf[3 * slot + 2];
+    }
+    constexpr int ND = CLS + 1;
+    const V3 o = v3m(r[0].x, r[0].y, r[0].z);
+    V3 dv[3], gv[NV];
+    dv[0] = v3m(0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 1; k < 3; ++k) dv[k] = k < ND ? vsub(v3m(r[k].x, r[k].y, r[k].z), o) : dv[0];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) gv[k] = vsub(g.v[k], o);
+    V3 q = closest_on_query<CLS, NV>(dv, gv);
+    Term t;
+    if (CLS == 0) {
+        t = point_term<GRAD>(make_float4(0.f, 0.f, 0.f, r[0].w), q.x, q.y, q.z);
+    } else if (CLS == 1) {
+        t = edge_term<GRAD>(make_float4(0.f, 0.f, 0.f, r[0].w), make_float4(dv[1].x, dv[1].y, dv[1].z, r[1].w),
+                            q.x, q.y, q.z, A.S, T.slogA, A.inv_alpha, metric);
+    } else {
+        t = tri_term<GRAD>(make_float4(0.f, 0.f, 0.f, r[0].w), make_float4(dv[1].x, dv[1].y, dv[1].z, r[1].w),
+                           make_float4(dv[2].x, dv[2].y, dv[2].z, r[2].w), q.x, q.y, q.z, A, T.slogA, metric);
+    }
+    t.err = fmaf(0x1p-20f, fabsf(q.x) + fabsf(q.y) + fabsf(q.z), t.err);
+    return t;
+}
+
+// Alg. 1 step for a query primitive (compare node_visit): the box distance from
+// the per-axis gaps, max(mn - hi, 0) + min(mx - lo, 0), in FP32
+template <bool GRAD, int NV>
+__device__ __forceinline__ int node_visit_q(const TreeView &T, const EvalArgs &A, const QPrim<NV> &g, LSE &st,
+                                            float4 &lo, float4 &hi, int &node, float4 &leaf_lo) {
+    float dx = fmaxf(g.mn[0] - hi.x, 0.f) + fminf(g.mx[0] - lo.x, 0.f);
+    float dy = fmaxf(g.mn[1] - hi.y, 0.f) + fminf(g.mx[1] - lo.y, 0.f);
+    float dz = fmaxf(g.mn[2] - hi.z, 0.f) + fminf(g.mx[2] - lo.z, 0.f);
+    float D2 = dot3(dx, dy, dz, dx, dy, dz);
+    float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
+    float diag2 = dot3(ex, ey, ez, ex, ey, ez);
+    int esc = __float_as_int(lo.w);
+    int pay = __float_as_int(hi.w);
+    float logn = pay < 0 ? 0.f : hi.w;
+    bool far = diag2 < A.beta2 * D2;
+    bool leaf = !far && pay < 0;
+    int slot = -1;
+    if (leaf) {
+        slot = pay & 0x7fffffff;
+        leaf_lo = lo;
+    }
+    node = (far || leaf) ? esc : node + 1;
+    if (node >= 0) load_node(T, node, lo, hi);
+    if (far) {
+        float D = fsqrt(D2);
+        float inv = frcp(D);
+        lse_add<GRAD>(st, D * A.far_scale, logn + T.slogA, dx * inv, dy * inv, dz * inv, A.alpha);
+    }
+    return slot;
+}
+
+// Alg. 1 over one class hierarchy for query primitives, with the same
+// wave-cooperative leaf stage as the point traversal (the owner's vertices
+// travel by lane shuffles)
+template <int CLS, bool GRAD, int NV>
+__device__ __forceinline__ void traverse_q(const TreeView &T, const EvalArgs &A, const QPrim<NV> &g, LSE &st,
+                                           LeafQueue &lq) {
+    const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
+    int node = T.n_nodes > 0 ? 0 : -1;
+    float4 leaf_lo = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (node >= 0 && st.s == 0.0 && st.dref == INFINITY) {
+        // any vertex of g bounds the distance to the seed leaf from above
+        float sd = seed_distance(T, g.v[0].x, g.v[0].y, g.v[0].z, A.inv_alpha);
+        if (sd == sd) {
+            st.dref = sd;
+            st.lref = 0.f;
+        }
+    }
+    float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+    if (node >= 0) load_node(T, node, lo, hi);
+    if (CLS == 0 || A.defer == 0) {
+        if (__builtin_amdgcn_sicmp(node, 0, 39) != 0) {
+            do {
+                if (node >= 0) {
+                    int slot = node_visit_q<GRAD, NV>(T, A, g, st, lo, hi, node, leaf_lo);
+                    if (slot >= 0) {
+                        Term t = leaf_term_q<CLS, GRAD, NV>(T, A, slot, leaf_lo, g, metric);
+                        lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
+                    }
+                }
+            } while (__builtin_amdgcn_sicmp(node, 0, 39) != 0);
+        }
+        return;
+    }
+    const int lane = __lane_id();
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int cnt = 0;
+    while (true) {
+        uint64_t live = __builtin_amdgcn_sicmp(node, 0, 39);
+        uint64_t room = __builtin_amdgcn_sicmp(cnt, kQ, 40);
+        bool go = ((live & room) != 0) & ((live & ~room) == 0);
+        if (go) {
+            do {
+                if (node >= 0 && cnt < kQ) {
+                    int slot = node_visit_q<GRAD, NV>(T, A, g, st, lo, hi, node, leaf_lo);
+                    if (slot >= 0) {
+                        lq.slot[cnt][lane] = slot;
+                        ++cnt;
+                    }
+                }
+                live = __builtin_amdgcn_sicmp(node, 0, 39);
+                room = __builtin_amdgcn_sicmp(cnt, kQ, 40);
+                go = ((live & room) != 0) & ((live & ~room) == 0);
+            } while (go);
+        }
+        if (__ballot(cnt > 0) == 0) break;
+        int off = 0, total = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            uint64_t m = __ballot((cnt >> b) & 1);
+            total += __popcll(m) << b;
+            off += __popcll(m & lt) << b;
+        }
+        for (int k = 0; k < cnt; ++k) lq.ent[off + k] = (lane << 3) | k;
+        wave_sync();
+        const uint64_t present = __ballot(true);
+        const int rank = __popcll(present & lt), npresent = __popcll(present);
+        for (int base = 0; base < total; base += npresent) {
+            int e = base + rank;
+            bool act = e < total;
+            int code = act ? lq.ent[e] : 0;
+            int owner = code >> 3, k = code & 7;
+            QPrim<NV> og;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                og.v[v] = v3m(__shfl(g.v[v].x, owner, 64), __shfl(g.v[v].y, owner, 64), __shfl(g.v[v].z, owner, 64));
+            if (act) {
+                Term t = leaf_term_q<CLS, GRAD, NV>(T, A, lq.slot[k][owner], leaf_lo, og, metric);
+                lq.res[k][0][owner] = fmaf(-A.cons, t.err, t.d);
+                lq.res[k][1][owner] = t.lw;
+                if (GRAD) {
+                    lq.res[k][2][owner] = t.gx;
+                    lq.res[k][3][owner] = t.gy;
+                    lq.res[k][4][owner] = t.gz;
+                }
+            }
+        }
+        wave_sync();
+        for (int k = 0; k < cnt; ++k) {
+            float gx = 0.f, gy = 0.f, gz = 0.f;
+            if (GRAD) { gx = lq.res[k][2][lane]; gy = lq.res[k][3][lane]; gz = lq.res[k][4][lane]; }
+            lse_add<GRAD>(st, lq.res[k][0][lane], lq.res[k][1][lane], gx, gy, gz, A.alpha);
+        }
+        cnt = 0;
+        wave_sync();
+    }
+}
+
 // Spread consecutive logical blocks over one XCD: hardware dispatches workgroup
 // i to XCD i % 8, so logical block = start(XCD) + i / 8 keeps each XCD's L2 on
 // a contiguous range of (Morton-ordered) queries.
@@ -736,6 +1069,59 @@ k_query_keys(const float *__restrict__ Q, const uint32_t *__restrict__ idx, int6
 // (miss: +inf).  Each step is one full Alg. 1 / Alg. 2 evaluation (value only)
 // inside this kernel; a lane whose ray has ended leaves the loop, and the
 // traversal's wave-cooperative leaf stage works with the lanes still present.
+// value + gradient for query primitives with NV vertices (G: n x NV x 3)
+template <int NV, int MASK>
+__global__ void __launch_bounds__(kB) k_evalq(EvalArgs A, const float *__restrict__ G) {
+    int i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
+    if (i >= A.nthr) return;
+    int qi = A.perm ? (int)A.perm[i] : i;
+    if ((unsigned)qi >= (unsigned)A.nq) return;
+    QPrim<NV> g;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const float *p = G + 3 * ((int64_t)qi * NV + v);
+        g.v[v] = v3m(p[0], p[1], p[2]);
+    }
+    g.mn[0] = g.mx[0] = g.v[0].x;
+    g.mn[1] = g.mx[1] = g.v[0].y;
+    g.mn[2] = g.mx[2] = g.v[0].z;
+#pragma unroll
+    for (int v = 1; v < NV; ++v) {
+        g.mn[0] = fminf(g.mn[0], g.v[v].x); g.mx[0] = fmaxf(g.mx[0], g.v[v].x);
+        g.mn[1] = fminf(g.mn[1], g.v[v].y); g.mx[1] = fmaxf(g.mx[1], g.v[v].y);
+        g.mn[2] = fminf(g.mn[2], g.v[v].z); g.mx[2] = fmaxf(g.mx[2], g.v[v].z);
+    }
+    __shared__ LeafQueue lqs[(MASK & 6) ? kB / 64 : 1];
+    LeafQueue &lq = lqs[(MASK & 6) ? threadIdx.x / 64 : 0];
+    LSE st;
+    lse_init(st);
+    if (MASK & 1) traverse_q<0, true, NV>(A.tree[0], A, g, st, lq);
+    if (MASK & 2) traverse_q<1, true, NV>(A.tree[1], A, g, st, lq);
+    if (MASK & 4) traverse_q<2, true, NV>(A.tree[2], A, g, st, lq);
+    finalize<true>(A, st, qi);
+}
+
+__global__ void __launch_bounds__(kB)
+k_centroids(const float *__restrict__ G, int nv, int64_t n, float *__restrict__ C) {
+    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= n) return;
+    float c[3] = {0.f, 0.f, 0.f};
+    for (int v = 0; v < nv; ++v)
+        for (int a = 0; a < 3; ++a) c[a] += G[3 * (i * nv + v) + a];
+    for (int a = 0; a < 3; ++a) C[3 * i + a] = c[a] / (float)nv;
+}
+
+template <int NV>
+void launch_evalq(const EvalArgs &A, const float *G, int mask, unsigned grid, hipStream_t s) {
+    switch (mask & 7) {
+#define SD_CASE(m) \
+    case m: hipLaunchKernelGGL((k_evalq<NV, m>), dim3(grid), dim3(kB), 0, s, A, G); break;
+        SD_CASE(1) SD_CASE(2) SD_CASE(3) SD_CASE(4) SD_CASE(5) SD_CASE(6) SD_CASE(7)
+#undef SD_CASE
+        default: break;
+    }
+}
+
 struct TraceArgs {
     const float *O, *U;
     float level, eps, t_max;
@@ -944,6 +1330,40 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
     }
     SD_HIP(hipGetLastError());
     if (perm) SD_HIP(hipFreeAsync(perm, s));
+    return SD_OK;
+}
+
+int evalq_dispatch(const sd_scene *sc, const float *G, int nv, int64_t n, const sd_params *p, float *d_out,
+                   float *g_out, hipStream_t s) {
+    if (n == 0) return SD_OK;
+    if (n > (int64_t)0x7fffffff - kB) return fail(SD_EUNSUPPORTED, "more than 2^31 query primitives per call");
+    EvalArgs A;
+    const int mask = make_args(sc, p, A) & 7;
+    A.nq = (int32_t)n;
+    A.nthr = (int32_t)n;
+    A.d_out = d_out;
+    A.g_out = g_out;
+    const unsigned grid = (unsigned)((n + kB - 1) / kB);
+    if (mask == 0) {   // empty scene: the empty sum
+        A.Q = G;   // unused by the brute kernel when every class is empty
+        hipLaunchKernelGGL(k_brute<true>, dim3(grid), dim3(kB), 0, s, A, (int64_t)0, (int64_t)0, (int64_t)0);
+        SD_HIP(hipGetLastError());
+        return SD_OK;
+    }
+    uint32_t *perm = nullptr;
+    float *cen = nullptr;
+    if (!(p->flags & SD_NO_QUERY_SORT) && n >= 4096) {
+        SD_HIP(hipMallocAsync((void **)&cen, n * 3 * sizeof(float), s));
+        SD_HIP(hipMallocAsync((void **)&perm, n * sizeof(uint32_t), s));
+        hipLaunchKernelGGL(k_centroids, dim3(grid), dim3(kB), 0, s, G, nv, n, cen);
+        SD_TRY(query_order(sc, cen, n, perm, s));
+        A.perm = perm;
+    }
+    if (nv == 2) launch_evalq<2>(A, G, mask, grid, s);
+    else launch_evalq<3>(A, G, mask, grid, s);
+    SD_HIP(hipGetLastError());
+    if (perm) SD_HIP(hipFreeAsync(perm, s));
+    if (cen) SD_HIP(hipFreeAsync(cen, s));
     return SD_OK;
 }
 

@@ -118,6 +118,9 @@ int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, 
                 const uint32_t *idx = nullptr);
 // nthr >= 0 with perm_in: nthr threads evaluate the queries perm_in[0..nthr)
 // out of nq; results land at the original query indices.
+// value + gradient for edge (nv = 2) or triangle (nv = 3) query primitives (eval.hip)
+int evalq_dispatch(const sd_scene *sc, const float *G, int nv, int64_t n, const sd_params *p, float *d_out,
+                   float *g_out, hipStream_t s);
 // sphere tracing of the level set d = level along rays (O, U) (eval.hip)
 int trace_dispatch(const sd_scene *sc, const float *O, const float *U, int64_t n, const sd_params *p,
                    float level, float eps, float t_max, int32_t max_steps, float *t_out, int32_t *steps_out,
