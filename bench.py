@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--ablation-res", type=int, default=256, help="image side of the beta ablation renders")
     ap.add_argument("--prims", action="store_true",
                     help="edges and triangles as query primitives on the benchmark scene (Sec. 3.4)")
+    ap.add_argument("--contact", action="store_true",
+                    help="rigid-body contact steps of the street body dropped on the street (Sec. 4.5)")
     ap.add_argument("--switch-study", action="store_true",
                     help="near/far switch discrepancy beta 0.5 vs 0.5001 on the street points (Sec. 4.3 analogue)")
     ap.add_argument("--sur-train", type=int, default=20_000_000, help="surrogate training samples")
@@ -281,6 +283,8 @@ def main():
         out["precision_sweep"] = sweep_leg(args, np, torch, api, scenes)
     if args.prims:
         out["query_primitives"] = prims_leg(args, np, torch, api, scenes, sc, scene)
+    if args.contact:
+        out["contact"] = contact_leg(args, np, torch, api, scenes)
     if args.beta_ablation:
         out["beta_ablation"] = beta_ablation_leg(args, np, torch, api, scenes)
     if args.switch_study:
@@ -345,6 +349,36 @@ def prims_leg(args, np, torch, api, scenes, sc, scene):
                                                                            device="cuda")].cpu().numpy() > dm))}
         out[name] = row
     return out
+
+
+def contact_leg(args, np, torch, api, scenes):
+    """Frictionless rigid-body contact (Sec. 4.5): the street body (a torus of
+    25,000 vertices) dropped from 1 m onto the street scene at scale 0.1;
+    implicit steps of 10 ms, each a primal-dual interior-point solve of one
+    smooth-distance constraint (value and gradient on the GPU)."""
+    from paper_2108_10480_amd import contact as C
+    sc, body_v = scenes.street_scene(0.1)
+    scene = api.upload_scene(sc)
+    lo, hi = scenes.scene_aabb(sc)
+    start = (0.5 * (lo[0] + hi[0]), 0.0, float(hi[2]) + 1.0)
+    body = C.RigidBody(body_v, mass=10.0, p=start, omega=(0.0, 0.5, 0.2))
+    step = C.ContactStep(scene, alpha=50.0, alpha_q=50.0, d_safe=0.05, h=0.01)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, evals0 = [], step.evals
+    nsteps = 60
+    for _ in range(nsteps):
+        it, c = step.step(body)
+        iters.append(it)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    evals = step.evals - evals0
+    return {"workload": f"street scene at scale 0.1 ({sc.counts()[0]} points, {sc.counts()[1]} wire segments, "
+                        f"{sc.counts()[2]} triangles); body of {len(body_v)} vertices dropped from 1 m, "
+                        f"alpha=alpha_q=50, d_safe=0.05, h=0.01, {nsteps} steps",
+            "ms_per_step": dt / nsteps * 1e3, "ipm_iterations_mean": float(np.mean(iters)),
+            "constraint_evaluations": evals, "ms_per_evaluation": dt / evals * 1e3,
+            "final_height": float(body.p[2] - hi[2]), "final_speed": float(np.linalg.norm(body.v))}
 
 
 def beta_ablation_leg(args, np, torch, api, scenes):

@@ -1,0 +1,54 @@
+"""GPU: rigid-body contact with one smooth-distance constraint (Sec. 4.5).
+Free flight reproduces the implicit / exponential Euler step exactly (the
+constraint is inactive); a body dropped on a point-sampled plane comes to
+rest with every accepted iterate feasible and no vertex through the plane."""
+import numpy as np
+import pytest
+
+from paper_2108_10480_amd import contact as C
+from tests.gpu_common import api, require_gpu, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _cube(n=5, side=0.2):
+    g = (np.arange(n) / (n - 1) - 0.5) * side
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    return np.column_stack([X.ravel(), Y.ravel(), Z.ravel()])
+
+
+def test_free_flight_is_the_unconstrained_step():
+    require_gpu()
+    scene = api.upload_scene(scenes.Scene(V=np.array([[0.0, 0.0, -100.0]], np.float32), P=np.array([0], np.int32)))
+    body = C.RigidBody(_cube(), mass=2.0, p=(0.0, 0.0, 1.0), v=(0.5, 0.0, 1.0), omega=(0.3, -0.2, 2.0))
+    R0, w = body.R.copy(), body.omega.copy()
+    step = C.ContactStep(scene, alpha=50.0, alpha_q=50.0, h=0.01)
+    p, v = body.p.copy(), body.v.copy()
+    for _ in range(10):
+        step.step(body)
+        v = v + step.h * step.g
+        p = p + step.h * v
+    np.testing.assert_allclose(body.p, p, atol=1e-7)
+    np.testing.assert_allclose(body.v, v, atol=1e-5)
+    np.testing.assert_allclose(body.omega, w, atol=1e-6)           # no torque: exponential Euler keeps omega
+    np.testing.assert_allclose(body.R, np.linalg.matrix_power(C.rotvec_to_matrix(0.01 * w), 10) @ R0, atol=1e-6)
+
+
+def test_drop_on_point_plane_comes_to_rest_without_penetration():
+    require_gpu()
+    g = np.arange(-1.0, 1.0001, 0.05)
+    X, Y = np.meshgrid(g, g)
+    P = np.column_stack([X.ravel(), Y.ravel(), np.zeros(X.size)]).astype(np.float32)
+    scene = api.upload_scene(scenes.Scene(V=P, P=np.arange(len(P), dtype=np.int32)))
+    body = C.RigidBody(_cube(), mass=1.0, p=(0.05, -0.02, 0.35), omega=(0.0, 0.0, 1.0))
+    d_safe = 0.05   # above the largest distance from the plane to its sample points (0.035)
+    step = C.ContactStep(scene, alpha=100.0, alpha_q=100.0, d_safe=d_safe, h=0.01)
+    lowest = []
+    for _ in range(60):
+        it, c = step.step(body)
+        assert c > 0 and it < step.max_iter
+        Xw = body.X.astype(np.float64) @ body.R.T + body.p
+        lowest.append(Xw[:, 2].min())
+    assert min(lowest) > 0.0                    # no vertex reached the plane
+    assert np.linalg.norm(body.v) < 0.05        # at rest
+    assert 0.0 < lowest[-1] < 2 * d_safe        # resting on the constraint, not hovering
