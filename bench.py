@@ -39,6 +39,12 @@ B_NODE = 32                  # one hierarchy node record
 B_TRI_LEAF = 48              # one triangle leaf record
 
 
+def _progress(msg):
+    """One line on stderr as each stage of the run starts (stdout keeps the
+    single JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def _sha(path):
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -76,8 +82,11 @@ def main():
     ap.add_argument("--rigid-steps", type=int, default=5)
     ap.add_argument("--sweep", action="store_true",
                     help="also run the alpha / precision sweep on the terrain + mesh scene")
-    ap.add_argument("--sweep-scale", type=float, default=0.1,
+    ap.add_argument("--sweep-scale", type=float, default=1.0,
                     help="size of the sweep scene relative to 20M points, 1M triangles, 200k edges, 32M queries")
+    ap.add_argument("--sweep-oracle", type=int, default=2000,
+                    help="queries of the sweep checked against the FP64 oracle (brute-force minimum distance "
+                         "over every primitive, Barnes-Hut on the exported hierarchies)")
     ap.add_argument("--beta-ablation", action="store_true",
                     help="sphere-trace renders of vertex, edge and triangle scenes over beta (Sec. 4.3 analogue)")
     ap.add_argument("--ablation-res", type=int, default=256, help="image side of the beta ablation renders")
@@ -117,6 +126,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    _progress("icosphere scene and queries")
     t_gen = time.time()
     sc = scenes.bumpy_icosphere(level=args.level, seed=2)
     Q = scenes.icosphere_queries(sc, args.nq, seed_box=3, seed_surf=4)
@@ -126,6 +136,7 @@ def main():
     Qd = torch.as_tensor(Q, device=dev)
     torch.cuda.synchronize()
 
+    _progress("hierarchy build")
     # hierarchy build (a1-a3), timed on its own
     builds = []
     for _ in range(2):
@@ -241,6 +252,7 @@ def main():
     }
 
     if not args.no_cpu_baseline:
+        _progress("FP64 oracle on the host (cpu baseline, parity sample)")
         from oracle import oracle as O
         rng = np.random.default_rng(123)
         k = n if args.cpu_sample <= 0 else min(args.cpu_sample, n)
@@ -276,18 +288,25 @@ def main():
                                 "conservative_violations": int(np.sum(d_s > dr)),
                                 "n": len(d_s)}
     if not args.no_surrogate:
+        _progress("surrogate")
         out["surrogate"] = surrogate_leg(args, sc, scene, np, torch, api, scenes)
     if not args.no_rigid:
+        _progress("rigid")
         out["rigid"] = rigid_leg(args, np, torch, api, scenes)
     if args.sweep:
+        _progress("precision sweep")
         out["precision_sweep"] = sweep_leg(args, np, torch, api, scenes)
     if args.prims:
+        _progress("query primitives")
         out["query_primitives"] = prims_leg(args, np, torch, api, scenes, sc, scene)
     if args.contact:
+        _progress("contact")
         out["contact"] = contact_leg(args, np, torch, api, scenes)
     if args.beta_ablation:
+        _progress("beta ablation")
         out["beta_ablation"] = beta_ablation_leg(args, np, torch, api, scenes)
     if args.switch_study:
+        _progress("switch study")
         out["switch_study"] = switch_study_leg(args, np, torch, api, scenes)
     print(json.dumps(out))
 
@@ -497,7 +516,7 @@ def sweep_leg(args, np, torch, api, scenes):
     perm = torch.empty(nq, dtype=torch.int32, device="cuda")
     d = torch.empty(nq, device="cuda")
     g = torch.empty((nq, 3), device="cuda")
-    n_or = min(20000, nq)
+    n_or = max(min(args.sweep_oracle, nq), 1)
     Qs = Q[:n_or].contiguous()
     res = {"workload": f"terrain {sc.counts()[0]} points + torus {sc.counts()[2]} triangles + "
                        f"hemisphere net {sc.counts()[1]} edges; {nq} queries in the box enlarged by 10 %, "
@@ -511,6 +530,7 @@ def sweep_leg(args, np, torch, api, scenes):
         lo, hi = scenes.scene_aabb(sc)
         floor = 1e-3 * float(np.linalg.norm(hi - lo))
     for alpha in (10.0, 100.0, 1000.0, 5000.0):
+        _progress(f"precision sweep: alpha {alpha:g}")
         row = {}
         for mode, fl in (("fp32", 0), ("fp64_root_log", api.SD_ROOTLOG_F64)):
             def run():
@@ -534,6 +554,7 @@ def sweep_leg(args, np, torch, api, scenes):
         if have_oracle:
             Qh = Qs.cpu().numpy().astype(np.float64)
             if "dmin" not in res:
+                _progress(f"precision sweep: brute-force minimum distance of {len(Qh)} queries on the host")
                 res["dmin"] = O.dmin(osc, Qh)
             dr, _, st = O.barnes_hut(osc, trees, Qh, alpha, beta, cut_f32=True)
             for mode, (dn, dc) in row.pop("_gpu").items():
