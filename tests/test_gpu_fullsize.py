@@ -52,3 +52,83 @@ def test_full_size_icosphere_in_benchmark_launch(alpha):
     compare(dp[idx], gp[idx], dr, gr, floor_of(sc), what=f"full size alpha={alpha:g}", dmin=dm)
     assert np.all(dc[idx] <= dr)           # conservative against the exact sum of the same terms
     assert np.all(dc[idx] <= dm)           # and against the minimum distance (App. A)
+
+
+def test_full_size_street_rigid_step_in_benchmark_launch():
+    """The rigid-body street workload at full size (2M points, 20,000 wire
+    segments, the 50,000-triangle torus at rest; 256 placements of the
+    25,000-vertex body = 6.4M queries) in the benchmark's launch: rigid
+    transform, query ordering, ordered value + gradient, query-mesh
+    log-sum-exp per placement (Eq. 6-8), adjoint of sum_k D_k.  2,000 sampled
+    queries against the oracle's Barnes-Hut on the exported hierarchies; three
+    whole placements through the oracle composite (D_k, and the adjoint in
+    t_k and R_k from the oracle's weights and gradients); the reduction
+    identity sum_j xbar_j = sum_k R_k^T tbar_k on every output."""
+    require_gpu()
+    from oracle import qmesh as QM
+    from tests.gpu_common import oracle_scene, oracle_trees
+    alpha, beta, alpha_q = 50.0, 0.5, 50.0
+    sc, body = scenes.street_scene(1.0)
+    scene = api.upload_scene(sc)
+    R, t = scenes.rigid_transforms(256, seed=5)
+    K, m = R.shape[0], body.shape[0]
+    X, Rd, td = cuda(body), cuda(R), cuda(t)
+    Q = api.sd_rigid_transform(X, Rd, td)
+    perm = api.sd_query_order(scene, Q)
+    d, g = api.sd_eval_grad_ordered(scene, Q, perm, alpha, beta, flags=api.SD_NO_CONSERVATIVE_ROUNDING)
+    D, w, _ = api.sd_query_mesh_lse(d.reshape(K, m), None, alpha_q, want_vgrad=False)
+    Rb, tb, Xb = api.sd_rigid_adjoint(X, Rd, w, g)
+    torch.cuda.synchronize()
+    Qn, dn, gn = Q.cpu().numpy().astype(np.float64), d.cpu().numpy(), g.cpu().numpy()
+    D, Rb, tb, Xb = (a.cpu().numpy().astype(np.float64) for a in (D, Rb, tb, Xb))
+    assert np.all(np.isfinite(dn)) and np.all(np.isfinite(gn)) and np.all(np.isfinite(D))
+    osc, trees, floor = oracle_scene(sc), oracle_trees(scene), floor_of(sc)
+    idx = np.sort(np.random.default_rng(8).choice(K * m, 2000, replace=False))
+    dr, gr, _ = O.barnes_hut(osc, trees, Qn[idx], alpha, beta, cut_f32=True)
+    compare(dn[idx], gn[idx], dr, gr, floor, what="street full size", dmin=O.dmin(osc, Qn[idx]))
+    ks = np.array([0, 101, 255])
+    rows = (ks[:, None] * m + np.arange(m)).reshape(-1)
+    dk, gk, _ = O.barnes_hut(osc, trees, Qn[rows], alpha, beta, cut_f32=True)
+    Dr, wr, _ = QM.query_mesh_lse(dk.reshape(3, m), gk.reshape(3, m, 3), alpha_q)
+    assert np.all(np.abs(D[ks] - Dr) <= 1e-5 * np.maximum(np.abs(Dr), floor))
+    Rr, tr, _ = O.rigid_adjoint(body, R[ks], wr.reshape(-1), gk)
+    np.testing.assert_allclose(tb[ks], tr, atol=2e-4)          # |tbar_k| <= sum_j w_kj = 1
+    np.testing.assert_allclose(Rb[ks], Rr, atol=2e-4 * max(1.0, np.abs(body).max()))
+    lhs = Xb.sum(0)
+    rhs = np.einsum("kab,ka->b", R.astype(np.float64), tb)
+    np.testing.assert_allclose(lhs, rhs, atol=1e-3 * max(1.0, np.abs(rhs).max()))
+
+
+def test_full_size_terrain_alpha_and_precision_modes():
+    """The scale / precision workload at full size (20M terrain points, 1M
+    torus triangles, 199,200 hemisphere edges; 32M queries in the box enlarged
+    by 10 %), in the benchmark's launch, for alpha 10, 1000 and 5000 with the
+    FP32 final logarithm and the FP64 one: 500 sampled queries against the
+    oracle's Barnes-Hut on the exported hierarchies, every output finite, the
+    conservative result at or below the minimum distance on the sample."""
+    require_gpu()
+    from tests.gpu_common import oracle_scene, oracle_trees
+    beta = 0.5
+    sc = scenes.terrain_scene(1.0)
+    scene = api.upload_scene(sc)
+    nq = 32_000_000
+    Q = scenes.terrain_queries(sc, nq, seed=10)
+    Qd = cuda(Q)
+    perm = api.sd_query_order(scene, Qd)
+    osc, trees, floor = oracle_scene(sc), oracle_trees(scene), floor_of(sc)
+    idx = np.sort(np.random.default_rng(9).choice(nq, 500, replace=False))
+    Qs = Q[idx].astype(np.float64)
+    dm = O.dmin(osc, Qs)
+    d = torch.empty(nq, device="cuda")
+    g = torch.empty((nq, 3), device="cuda")
+    for alpha in (10.0, 1000.0, 5000.0):
+        dr, gr, _ = O.barnes_hut(osc, trees, Qs, alpha, beta, cut_f32=True)
+        for fl in (0, api.SD_ROOTLOG_F64):
+            api.sd_eval_grad_ordered(scene, Qd, perm, alpha, beta, flags=fl | api.SD_NO_CONSERVATIVE_ROUNDING,
+                                     out=d, grad_out=g)
+            dn, gn = d.cpu().numpy(), g.cpu().numpy()
+            assert np.all(np.isfinite(dn)) and np.all(np.isfinite(gn))
+            compare(dn[idx], gn[idx], dr, gr, floor, what=f"terrain full size alpha={alpha:g} flags={fl}", dmin=dm)
+            api.sd_eval_grad_ordered(scene, Qd, perm, alpha, beta, flags=fl, out=d, grad_out=g)
+            dc = d.cpu().numpy()
+            assert np.all(dc[idx] <= dr) and np.all(dc[idx] <= dm)
