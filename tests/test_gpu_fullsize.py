@@ -1,5 +1,6 @@
-"""GPU parity at the full size of the icosphere workload, in the launch the
-throughput benchmark times: the level-7 bumpy icosphere (327,680 triangles)
+"""GPU parity at the full sizes of the benchmark workloads (icosphere, street
+rigid step, terrain precision sweep, surrogate inference), each in the launch
+the benchmark times.  Icosphere: the level-7 bumpy icosphere (327,680 triangles)
 with 1,000,000 queries (half uniform in the box, half within 0.02 of the
 surface), Morton ordering of the queries, then the ordered value + gradient
 kernel over all of them.  Sampled outputs are compared one by one with the
@@ -132,3 +133,58 @@ def test_full_size_terrain_alpha_and_precision_modes():
             api.sd_eval_grad_ordered(scene, Qd, perm, alpha, beta, flags=fl, out=d, grad_out=g)
             dc = d.cpu().numpy()
             assert np.all(dc[idx] <= dr) and np.all(dc[idx] <= dm)
+
+
+def test_full_size_surrogate_inference_and_routing():
+    """The surrogate workload's inference at full size (16M uniform queries
+    against the level-7 icosphere) in the benchmark's launch (the fused
+    network kernel with routing, exact Barnes-Hut for the routed queries).
+    The network's weights are the seeded initialisation scaled by 2 (the
+    kernel's arithmetic does not depend on training): 1,000 sampled value +
+    input-gradient outputs against the FP64 network oracle within the BF16
+    rounding envelope; on every query the routing flag is |y| < band + eps
+    and unrouted outputs are the network's bit for bit; 1,000 sampled routed
+    queries against the oracle's Barnes-Hut on the exported hierarchy."""
+    require_gpu()
+    from paper_2108_10480_amd import surrogate as S
+    from tests import surrogate_ref as R
+    from tests.test_gpu_surrogate import K_ENV, _surrogate
+    w = _workload()
+    sc, scene = w["sc"], w["scene"]
+    n = 16_000_000
+    X = scenes.uniform_queries(n, 8, -1.5, 1.5)
+    Xd = cuda(X)
+    sur, th, B = _surrogate(seed=17, scale=2.0)
+    y, gy = sur.forward(Xd)
+    band, eps = 0.05, 0.02
+    sur.load(th, eps_cert=eps)
+    d, g, routed, nfb = S.sd_eval_surrogate(scene, sur, Xd, 50.0, 0.5, band=band)
+    torch.cuda.synchronize()
+    y, gy, d, g = y.cpu().numpy(), gy.cpu().numpy(), d.cpu().numpy(), g.cpu().numpy()
+    routed = routed.cpu().numpy().astype(bool)
+    assert np.all(np.isfinite(y)) and np.all(np.isfinite(gy))
+    # network parity on a sample
+    idx = np.sort(np.random.default_rng(19).choice(n, 1000, replace=False))
+    Xs = X[idx].astype(np.float64)
+    ref, dev = R.envelope(R.infer, R.effective_theta(th), B.astype(np.float64), Xs)
+    yr, gr = ref[:1000], ref[1000:].reshape(1000, 3)
+    yd, gd = dev[:1000], dev[1000:].reshape(1000, 3)
+    fy = 2.0 ** -16 * (np.abs(yr) + np.abs(yr).mean())
+    fg = 2.0 ** -16 * (np.abs(gr) + np.abs(gr).mean())
+    assert np.all(np.abs(y[idx] - yr) <= K_ENV * yd + fy)
+    assert np.all(np.abs(gy[idx] - gr) <= K_ENV * gd + fg)
+    # routing on every query
+    want = np.abs(y) < np.float32(band) + np.float32(eps)
+    assert np.array_equal(routed, want) and nfb == int(want.sum()) and 0 < nfb < n
+    assert np.array_equal(d[~routed], y[~routed]) and np.array_equal(g[~routed], gy[~routed])
+    # routed queries: the exact path
+    r = np.flatnonzero(routed)
+    rs = np.sort(np.random.default_rng(20).choice(r, min(1000, len(r)), replace=False))
+    Qs = X[rs].astype(np.float64)
+    dr, grr, _ = O.barnes_hut(w["osc"], w["trees"], Qs, 50.0, 0.5, cut_f32=True)
+    dm = O.dmin(w["osc"], Qs)
+    assert np.all(d[rs] <= dr) and np.all(d[rs] <= dm)      # default conservative rounding
+    dp, gp, rp, _ = S.sd_eval_surrogate(scene, sur, Xd, 50.0, 0.5, band=band, flags=api.SD_NO_CONSERVATIVE_ROUNDING)
+    assert torch.equal(rp.cpu(), torch.as_tensor(routed).to(rp.dtype))
+    dp, gp = dp.cpu().numpy(), gp.cpu().numpy()
+    compare(dp[rs], gp[rs], dr, grr, floor_of(sc), what="routed full size", dmin=dm)
