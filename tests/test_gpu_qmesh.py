@@ -67,6 +67,40 @@ def test_mixed_query_mesh_matches_oracle():
     assert torch.equal(D2, D)
 
 
+@pytest.mark.parametrize("beta", [0.0, 0.5])
+def test_triangle_query_mesh_end_to_end(beta):
+    """A triangle query mesh (a torus beside a bumpy sphere): the distances
+    and gradients of its triangles from the query-primitive traversal
+    (Sec. 3.4), combined by Eq. 6-8, against the oracle's query-primitive
+    Barnes-Hut (FP32 opening decisions) combined by the oracle's Eq. 6-8.
+    Tolerances follow from the per-primitive ones (value 2e-5, gradient 1e-3
+    for triangles on triangles): D is a log-sum-exp of the d_j, so its
+    relative error is at most theirs; w_j = softmin weights move by about
+    alpha_q |delta d_j|; the vertex gradients mix the gradient errors."""
+    require_gpu()
+    from tests.gpu_common import oracle_trees
+    data = scenes.bumpy_icosphere(level=3, seed=5)
+    scene = api.upload_scene(data)
+    tv, tf = scenes.torus_grid(24, 12, 0.5, 0.15)
+    tv = (tv + np.array([2.3, 0.0, 0.2])).astype(np.float32)     # clear of the sphere (radius <= 1.4)
+    G = tv[tf].astype(np.float32)
+    alpha, alpha_q = 40.0, 30.0
+    d, g = api.sd_eval_grad_prims(scene, cuda(G), alpha, beta, flags=api.SD_NO_CONSERVATIVE_ROUNDING)
+    D, w, vg = api.sd_query_mesh_lse(d.reshape(1, -1), g.reshape(1, -1, 3), alpha_q,
+                                     prim=cuda(tf.astype(np.int32)), nV=len(tv))
+    torch.cuda.synchronize()
+    osc, trees = oracle_scene(data), oracle_trees(scene)
+    dr, gr, _ = O.barnes_hut_prims(osc, trees, G.astype(np.float64), alpha, beta, cut_f32=True)
+    _, _, dm = O.brute_prims(osc, G.astype(np.float64), alpha)
+    assert dm.min() > 0.1
+    Dr, wr, vr = QM.query_mesh_lse(dr[None], gr[None], alpha_q, tf.astype(np.int64), len(tv))
+    D, w, vg = D.cpu().numpy().astype(np.float64), w.cpu().numpy(), vg.cpu().numpy()
+    assert abs(D[0] - Dr[0]) <= 2e-5 * abs(Dr[0])
+    dd = np.abs(d.cpu().numpy() - dr).max()
+    np.testing.assert_allclose(w[0], wr[0], rtol=0, atol=3 * alpha_q * dd * wr.max() + 1e-7)
+    np.testing.assert_allclose(vg[0], vr[0], rtol=0, atol=1e-3 * np.abs(vr).max())
+
+
 def test_edge_cases():
     require_gpu()
     g = np.zeros((4, 3, 3), np.float32)
