@@ -106,6 +106,8 @@ int sd_build_bvh(const float *V, int64_t nV,
 /* Release a scene and its device memory.  NULL is ignored. */
 int sd_free_scene(sd_scene *scene);
 
+/* Sizes and weight scales of a built scene (host struct, filled
+ * synchronously without device work).  SD_EINVAL for NULL arguments. */
 int sd_scene_info_get(const sd_scene *scene, sd_scene_info *out_host);
 
 /*
@@ -295,6 +297,7 @@ typedef struct sd_surrogate sd_surrogate;
  * Synchronises `stream` once.  SD_ENOMEM when the workspace does not fit. */
 int sd_surrogate_create(const float *B_host, const float *theta_host, int64_t max_batch,
                         void *stream, sd_surrogate **out);
+/* Release a surrogate handle and its device memory.  NULL is ignored. */
 int sd_surrogate_free(sd_surrogate *sur);
 
 /* Surrogate value d_out (nQ) and, when grad_out is not NULL, its gradient in x
@@ -357,10 +360,10 @@ int sd_surrogate_load(sd_surrogate *sur, const float *theta_host, const float *m
 
 /* Smooth distance and gradient with the surrogate where it is certified:
  * every query gets the surrogate value y and gradient; the queries with
- * |y| < band + eps_cert (the certified margin of sd_surrogate_certify) are
- * (or, after sd_surrogate_certify_cells, < band + the margin of the query's
- * cell) are then evaluated exactly (sd_eval_grad semantics with `params`, in Morton
- * order unless SD_NO_QUERY_SORT) and overwritten.  routed (nQ bytes, may be
+ * |y| < band + eps_cert (the certified margin of sd_surrogate_certify; after
+ * sd_surrogate_certify_cells, band + the margin of the query's cell) are then
+ * evaluated exactly (sd_eval_grad semantics with `params`, in Morton order
+ * unless SD_NO_QUERY_SORT) and overwritten.  routed (nQ bytes, may be
  * NULL) receives 1 for those queries.  *n_fallback_host (may be NULL) receives
  * their number.  The surrogate must have been trained for this scene and
  * params.  Synchronises `stream` once (to size the exact pass). */
@@ -368,6 +371,8 @@ int sd_eval_surrogate(const sd_scene *scene, const sd_surrogate *sur, const floa
                       const sd_params *params, float band, float *d_out, float *grad_out,
                       uint8_t *routed, int64_t *n_fallback_host, void *stream);
 
+/* Message of the last failed call on this thread (thread-local storage owned
+ * by the library; valid until the next failing call on the thread). */
 const char *sd_last_error(void);
 
 #ifdef __cplusplus
