@@ -654,34 +654,74 @@ __device__ __forceinline__ float seg_seg(V3 p0, V3 p1, V3 q0, V3 q1, V3 &on_q) {
     return best;
 }
 
-// segment p0 p1 against triangle t0 t1 t2: squared distance, the closest point
-// on the segment (xs) and on the triangle (xt); a crossing gives 0
+// Quantities of a triangle a b c shared by every test against it: edge
+// vectors e1 = b - a, e2 = c - a, their Gram entries, the reciprocal of the
+// Gram determinant (0 for a degenerate triangle) and the normal e1 x e2.
+struct TriFrame {
+    V3 a, e1, e2, n;
+    float g11, g12, g22, inv;
+    bool ok;
+};
+__device__ __forceinline__ TriFrame tri_frame(V3 a, V3 b, V3 c) {
+    TriFrame f;
+    f.a = a;
+    f.e1 = vsub(b, a);
+    f.e2 = vsub(c, a);
+    f.n = vcross(f.e1, f.e2);
+    f.g11 = vdot(f.e1, f.e1);
+    f.g12 = vdot(f.e1, f.e2);
+    f.g22 = vdot(f.e2, f.e2);
+    float det = dop(f.g11, f.g22, f.g12, f.g12);
+    f.ok = det > 1e-12f * f.g11 * f.g22;
+    f.inv = f.ok ? frcp(det) : 0.f;
+    return f;
+}
+
+// Projection y of p onto the plane of the triangle; true when it falls inside
+// the triangle (the face region; tri_point's inside test)
+__device__ __forceinline__ bool face_proj(const TriFrame &f, V3 p, V3 &y) {
+    V3 r = vsub(p, f.a);
+    float r1 = vdot(f.e1, r), r2 = vdot(f.e2, r);
+    float u = dop(f.g22, r1, f.g12, r2) * f.inv, v = dop(f.g11, r2, f.g12, r1) * f.inv;
+    y = vaxpy(vaxpy(f.a, u, f.e1), v, f.e2);
+    return f.ok && u >= 0.f && v >= 0.f && u + v <= 1.f;
+}
+
+// Segment p0 p1 crossing the triangle t0 t1 t2 (frame f): the crossing point,
+// accepted when it lies on the triangle up to rounding
+__device__ __forceinline__ bool seg_crosses(V3 p0, V3 p1, const TriFrame &f, V3 t0, V3 t1, V3 t2, V3 &y) {
+    float s0 = vdot(f.n, vsub(p0, f.a)), s1 = vdot(f.n, vsub(p1, f.a));
+    if (!((s0 <= 0.f && s1 >= 0.f) || (s0 >= 0.f && s1 <= 0.f)) || s0 == s1) return false;
+    y = vaxpy(p0, s0 / (s0 - s1), vsub(p1, p0));
+    V3 z = tri_point(y, t0, t1, t2);
+    return vdist2(y, z) <= 1e-12f * (1.f + vdot(y, y));
+}
+
+// Segment p0 p1 against triangle t0 t1 t2: squared distance, the closest point
+// on the segment (xs) and on the triangle (xt); a crossing gives 0.  Apart
+// from a crossing, the closest pair is an endpoint against the face interior
+// or the segment against one of the triangle's edges (App. B's QP optimum lies
+// on those boundary faces).
 __device__ __forceinline__ float seg_tri(V3 p0, V3 p1, V3 t0, V3 t1, V3 t2, V3 &xs, V3 &xt) {
-    V3 n = vcross(vsub(t1, t0), vsub(t2, t0));
-    float s0 = vdot(n, vsub(p0, t0)), s1 = vdot(n, vsub(p1, t0));
-    if ((s0 <= 0.f && s1 >= 0.f) || (s0 >= 0.f && s1 <= 0.f)) {
-        if (s0 != s1) {
-            V3 y = vaxpy(p0, s0 / (s0 - s1), vsub(p1, p0));
-            V3 z = tri_point(y, t0, t1, t2);
-            float tol = 1e-12f * (1.f + vdot(y, y));
-            if (vdist2(y, z) <= tol) {
-                xs = y;
-                xt = z;
-                return 0.f;
-            }
-        }
+    const TriFrame f = tri_frame(t0, t1, t2);
+    V3 y;
+    if (seg_crosses(p0, p1, f, t0, t1, t2, y)) {
+        xs = y;
+        xt = y;
+        return 0.f;
     }
+    float best = INFINITY;
     xs = p0;
-    xt = tri_point(p0, t0, t1, t2);
-    float best = vdist2(p0, xt);
-    V3 z = tri_point(p1, t0, t1, t2);
-    float d = vdist2(p1, z);
-    if (d < best) { best = d; xs = p1; xt = z; }
+    xt = t0;
+    if (face_proj(f, p0, y)) { best = vdist2(p0, y); xt = y; }
+    if (face_proj(f, p1, y)) {
+        float d = vdist2(p1, y);
+        if (d < best) { best = d; xs = p1; xt = y; }
+    }
     V3 T3[3] = {t0, t1, t2};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        V3 y;
-        d = seg_seg(T3[k], T3[(k + 1) % 3], p0, p1, y);   // y on p0 p1
+        float d = seg_seg(T3[k], T3[(k + 1) % 3], p0, p1, y);   // y on p0 p1
         if (d < best) {
             best = d;
             xs = y;
@@ -689,6 +729,42 @@ __device__ __forceinline__ float seg_tri(V3 p0, V3 p1, V3 t0, V3 t1, V3 t2, V3 &
         }
     }
     return best;
+}
+
+// Triangle g against triangle t: the point of g closest to t.  The triangles
+// meet when an edge of one crosses the other; otherwise the closest pair is a
+// vertex of one against the other's face interior, or a pair of edges.
+__device__ __forceinline__ V3 tri_tri_on_g(const V3 (&t)[3], const V3 (&g)[3]) {
+    const TriFrame ft = tri_frame(t[0], t[1], t[2]), fg = tri_frame(g[0], g[1], g[2]);
+    V3 y;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (seg_crosses(g[k], g[(k + 1) % 3], ft, t[0], t[1], t[2], y)) return y;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (seg_crosses(t[k], t[(k + 1) % 3], fg, g[0], g[1], g[2], y)) return y;
+    float best = INFINITY;
+    V3 out = g[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (face_proj(ft, g[k], y)) {
+            float d = vdist2(g[k], y);
+            if (d < best) { best = d; out = g[k]; }
+        }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (face_proj(fg, t[k], y)) {
+            float d = vdist2(t[k], y);
+            if (d < best) { best = d; out = y; }
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            float d = seg_seg(t[i], t[(i + 1) % 3], g[j], g[(j + 1) % 3], y);   // y on g's edge
+            if (d < best) { best = d; out = y; }
+        }
+    return out;
 }
 
 template <int NV>
@@ -715,20 +791,8 @@ __device__ __forceinline__ V3 closest_on_query(const V3 (&dv)[3], const V3 (&gv)
         seg_tri(gv[0], gv[1], dv[0], dv[1], dv[2], xs, xt);
         return xs;
     }
-    // triangle against triangle: the closest pair involves an edge of one of them
-    float best = INFINITY;
-    V3 out = gv[0];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        float d = seg_tri(gv[k], gv[(k + 1) % NV], dv[0], dv[1], dv[2], xs, xt);
-        if (d < best) { best = d; out = xs; }
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        float d = seg_tri(dv[k], dv[(k + 1) % 3], gv[0], gv[1], gv[NV - 1], xs, xt);
-        if (d < best) { best = d; out = xt; }
-    }
-    return out;
+    const V3 g3[3] = {gv[0], gv[1], gv[NV - 1]};
+    return tri_tri_on_g(dv, g3);
 }
 
 // Leaf term for a query primitive: the point-query term at g(lambda).  Both
