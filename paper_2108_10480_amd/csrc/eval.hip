@@ -626,13 +626,15 @@ __device__ __forceinline__ V3 tri_point(V3 p, V3 a, V3 b, V3 c) {
     return best;
 }
 
-// closest points of segments p0 p1 and q0 q1: squared distance, point on q
-__device__ __forceinline__ float seg_seg(V3 p0, V3 p1, V3 q0, V3 q1, V3 &on_q) {
+// the interior stationary point of |x(s) - y(t)|^2 over the two segments, when
+// the segments are not (nearly) parallel and it lies inside both: squared
+// distance (else +inf), the point on q
+__device__ __forceinline__ float seg_seg_interior(V3 p0, V3 p1, V3 q0, V3 q1, V3 &on_q) {
     V3 u = vsub(p1, p0), v = vsub(q1, q0), w = vsub(p0, q0);
     float a = vdot(u, u), b = vdot(u, v), c = vdot(v, v), d = vdot(u, w), e = vdot(v, w);
     float best = INFINITY;
     float den = dop(a, c, b, b);
-    if (den > 1e-6f * a * c) {   // not (nearly) parallel: interior stationary point
+    if (den > 1e-6f * a * c) {
         float inv = frcp(den);
         float s = dop(b, e, c, d) * inv, t = dop(a, e, b, d) * inv;
         if (s >= 0.f && s <= 1.f && t >= 0.f && t <= 1.f) {
@@ -641,6 +643,13 @@ __device__ __forceinline__ float seg_seg(V3 p0, V3 p1, V3 q0, V3 q1, V3 &on_q) {
             on_q = y;
         }
     }
+    return best;
+}
+
+// closest points of segments p0 p1 and q0 q1: the interior stationary point or
+// an endpoint of one against the other; squared distance, point on q
+__device__ __forceinline__ float seg_seg(V3 p0, V3 p1, V3 q0, V3 q1, V3 &on_q) {
+    float best = seg_seg_interior(p0, p1, q0, q1, on_q);
     V3 y = seg_point(p0, q0, q1);
     float dd = vdist2(p0, y);
     if (dd < best) { best = dd; on_q = y; }
@@ -757,12 +766,25 @@ __device__ __forceinline__ V3 tri_tri_on_g(const V3 (&t)[3], const V3 (&g)[3]) {
             float d = vdist2(t[k], y);
             if (d < best) { best = d; out = y; }
         }
+    // edge pairs: the interior stationary points, then each vertex of one
+    // triangle against each edge of the other (every endpoint candidate of the
+    // nine segment pairs, each formed once)
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            float d = seg_seg(t[i], t[(i + 1) % 3], g[j], g[(j + 1) % 3], y);   // y on g's edge
+            float d = seg_seg_interior(t[i], t[(i + 1) % 3], g[j], g[(j + 1) % 3], y);   // y on g's edge
             if (d < best) { best = d; out = y; }
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            y = seg_point(t[i], g[j], g[(j + 1) % 3]);
+            float d = vdist2(t[i], y);
+            if (d < best) { best = d; out = y; }
+            d = vdist2(g[j], seg_point(g[j], t[i], t[(i + 1) % 3]));
+            if (d < best) { best = d; out = g[j]; }
         }
     return out;
 }
