@@ -1047,13 +1047,15 @@ __device__ __forceinline__ void lse_init(LSE &st) {
     st.s = st.gx = st.gy = st.gz = 0.0;
 }
 
-// Waves per SIMD the traversal is compiled for (register budget); the
-// default lets the compiler choose (about 115 registers, 4 waves).
-#ifdef SD_EVAL_WPE
-#define SD_EVAL_ATTR __attribute__((amdgpu_waves_per_eu(SD_EVAL_WPE, SD_EVAL_WPE)))
-#else
-#define SD_EVAL_ATTR
+// Waves per SIMD the traversal is compiled for (register budget): four, i.e.
+// at most 128 registers.  Single-class variants fit without it (triangles:
+// 124); the mixed-class ones would take 133-140 registers and run three
+// waves, and the fourth wave is worth about 6 % on the three-class street
+// scene at the cost of 12-20 bytes of spills.
+#ifndef SD_EVAL_WPE
+#define SD_EVAL_WPE 4
 #endif
+#define SD_EVAL_ATTR __attribute__((amdgpu_waves_per_eu(SD_EVAL_WPE, SD_EVAL_WPE)))
 
 template <bool GRAD, bool COUNT, int MASK>
 __global__ void __launch_bounds__(kB) SD_EVAL_ATTR k_eval(EvalArgs A) {
@@ -1156,8 +1158,13 @@ k_query_keys(const float *__restrict__ Q, const uint32_t *__restrict__ idx, int6
 // inside this kernel; a lane whose ray has ended leaves the loop, and the
 // traversal's wave-cooperative leaf stage works with the lanes still present.
 // value + gradient for query primitives with NV vertices (G: n x NV x 3)
+// Compiled for four waves per SIMD (at most 128 registers): the default
+// allocation takes 132-156 registers for edge and triangle data, three waves,
+// and the fourth wave's latency hiding is worth about 10 % (the few spills of
+// the triangle-on-triangle variants included).
 template <int NV, int MASK>
-__global__ void __launch_bounds__(kB) k_evalq(EvalArgs A, const float *__restrict__ G) {
+__global__ void __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_evalq(EvalArgs A, const float *__restrict__ G) {
     int i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
     if (i >= A.nthr) return;
     int qi = A.perm ? (int)A.perm[i] : i;
