@@ -57,35 +57,70 @@ __device__ inline int load_ids(const int32_t *ids, int64_t i, int64_t nV, int ou
     return ok;
 }
 
+// min / max over the 64 lanes of a wave (every lane takes part)
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o, 64));
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, o, 64));
+    return x;
+}
+
+// Primitive boxes, plus the scene-wide bounds, reduced over each wave first
+// so that one lane per wave updates the shared record (13 words that every
+// primitive would otherwise hit with an atomic).  Lanes past the end take
+// part in the reductions with neutral values.
 template <int K>
 __global__ void __launch_bounds__(kB)
 k_prim_boxes(const float *__restrict__ V, int64_t nV, const int32_t *__restrict__ ids, int64_t n,
              float4 *__restrict__ blo, float4 *__restrict__ bhi, Reduce *red) {
     int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i >= n) return;
-    int id[3];
-    load_ids<K>(ids, i, nV, id, &red->bad);
-    float lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = V[3 * (int64_t)id[0] + a];
-    for (int k = 1; k < K; ++k)
+    const bool live = i < n;
+    uint32_t cmn[3], cmx[3], bmn[3], bmx[3], dmx = 0u;
+    for (int a = 0; a < 3; ++a) { cmn[a] = bmn[a] = 0xffffffffu; cmx[a] = bmx[a] = 0u; }
+    if (live) {
+        int id[3];
+        load_ids<K>(ids, i, nV, id, &red->bad);
+        float lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) lo[a] = hi[a] = V[3 * (int64_t)id[0] + a];
+        for (int k = 1; k < K; ++k)
+            for (int a = 0; a < 3; ++a) {
+                float x = V[3 * (int64_t)id[k] + a];
+                lo[a] = fminf(lo[a], x);
+                hi[a] = fmaxf(hi[a], x);
+            }
+        blo[i] = make_float4(lo[0], lo[1], lo[2], 0.f);
+        bhi[i] = make_float4(hi[0], hi[1], hi[2], 0.f);
+        float dd = 0.f;
         for (int a = 0; a < 3; ++a) {
-            float x = V[3 * (int64_t)id[k] + a];
-            lo[a] = fminf(lo[a], x);
-            hi[a] = fmaxf(hi[a], x);
+            float c = 0.5f * (lo[a] + hi[a]);
+            cmn[a] = cmx[a] = f2o(c);
+            bmn[a] = f2o(lo[a]);
+            bmx[a] = f2o(hi[a]);
+            float e = hi[a] - lo[a];
+            dd = fmaf(e, e, dd);
         }
-    blo[i] = make_float4(lo[0], lo[1], lo[2], 0.f);
-    bhi[i] = make_float4(hi[0], hi[1], hi[2], 0.f);
-    float dd = 0.f;
-    for (int a = 0; a < 3; ++a) {
-        float c = 0.5f * (lo[a] + hi[a]);
-        atomicMin(&red->cmin[a], f2o(c));
-        atomicMax(&red->cmax[a], f2o(c));
-        atomicMin(&red->bmin[a], f2o(lo[a]));
-        atomicMax(&red->bmax[a], f2o(hi[a]));
-        float e = hi[a] - lo[a];
-        dd = fmaf(e, e, dd);
+        dmx = f2o(sqrtf(dd));
     }
-    atomicMax(&red->diam, f2o(sqrtf(dd)));
+    for (int a = 0; a < 3; ++a) {
+        cmn[a] = wave_min_u32(cmn[a]);
+        cmx[a] = wave_max_u32(cmx[a]);
+        bmn[a] = wave_min_u32(bmn[a]);
+        bmx[a] = wave_max_u32(bmx[a]);
+    }
+    dmx = wave_max_u32(dmx);
+    if ((threadIdx.x & 63) == 0) {
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&red->cmin[a], cmn[a]);
+            atomicMax(&red->cmax[a], cmx[a]);
+            atomicMin(&red->bmin[a], bmn[a]);
+            atomicMax(&red->bmax[a], bmx[a]);
+        }
+        atomicMax(&red->diam, dmx);
+    }
 }
 
 __global__ void __launch_bounds__(kB)
@@ -244,13 +279,18 @@ __global__ void __launch_bounds__(kB)
 k_edge_weights(const int32_t *__restrict__ E, int64_t nE, int64_t nV,
                const uint32_t *__restrict__ cnt, float *__restrict__ wt, Reduce *red) {
     int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i >= nE) return;
-    int a = E[2 * i], b = E[2 * i + 1];
-    if (a < 0 || a >= nV || b < 0 || b >= nV) return;
-    uint32_t na = cnt[a], nb = cnt[b];
-    wt[2 * i] = 1.0f / (float)na;
-    wt[2 * i + 1] = 1.0f / (float)nb;
-    atomicMax(&red->maxv, na > nb ? na : nb);
+    uint32_t vmax = 0;
+    if (i < nE) {
+        int a = E[2 * i], b = E[2 * i + 1];
+        if (a >= 0 && a < nV && b >= 0 && b < nV) {
+            uint32_t na = cnt[a], nb = cnt[b];
+            wt[2 * i] = 1.0f / (float)na;
+            wt[2 * i + 1] = 1.0f / (float)nb;
+            vmax = na > nb ? na : nb;
+        }
+    }
+    vmax = wave_max_u32(vmax);   // one atomic per wave
+    if ((threadIdx.x & 63) == 0) atomicMax(&red->maxv, vmax);
 }
 
 __global__ void __launch_bounds__(kB)
@@ -284,26 +324,40 @@ k_tri_weights(const int32_t *__restrict__ T, int64_t nT, int64_t nV,
               const uint32_t *__restrict__ vcnt, const uint32_t *__restrict__ ecount,
               float *__restrict__ wt, uint32_t *__restrict__ present, Reduce *red) {
     int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i >= nT) return;
+    const bool live = i < nT;
     uint32_t v = 0, e = 0;
-    for (int s = 0; s < 3; ++s) {
-        int a = T[3 * i + s];
-        if (a >= 0 && a < nV) v = max(v, vcnt[a]);
-        e = max(e, ecount[3 * i + s]);
+    if (live) {
+        for (int s = 0; s < 3; ++s) {
+            int a = T[3 * i + s];
+            if (a >= 0 && a < nV) v = max(v, vcnt[a]);
+            e = max(e, ecount[3 * i + s]);
+        }
+        if (v <= 1) {
+            wt[3 * i] = 1.f; wt[3 * i + 1] = 1.f; wt[3 * i + 2] = 1.f;
+        } else {
+            wt[3 * i] = 1.0f / (float)v;
+            wt[3 * i + 1] = 1.0f / (float)e;
+            wt[3 * i + 2] = (float)((double)(v - 1) / (double)v);
+        }
     }
-    if (v <= 1) {
-        wt[3 * i] = 1.f; wt[3 * i + 1] = 1.f; wt[3 * i + 2] = 1.f;
-    } else {
-        wt[3 * i] = 1.0f / (float)v;
-        wt[3 * i + 1] = 1.0f / (float)e;
-        wt[3 * i + 2] = (float)((double)(v - 1) / (double)v);
-    }
-    atomicMax(&red->maxv, v);
-    if (v < 1024 && e < 1024) {
-        uint32_t bit = v * 1024 + e;
-        atomicOr(&present[bit >> 5], 1u << (bit & 31));
-    } else {
-        atomicOr(&red->bad, 2u);
+    // one atomic per wave for the largest valence; the (v, e) class bits are
+    // set by one lane per distinct class in the wave (usually one)
+    uint32_t vmax = wave_max_u32(v);
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) atomicMax(&red->maxv, vmax);
+    const bool fits = v < 1024 && e < 1024;
+    if (live && !fits) atomicOr(&red->bad, 2u);
+    const uint32_t bit = v * 1024 + e;
+    bool pending = live && fits;
+    while (true) {
+        uint64_t m = __ballot(pending);
+        if (m == 0) break;
+        int leader = __ffsll((unsigned long long)m) - 1;
+        uint32_t lb = (uint32_t)__shfl((int)bit, leader, 64);
+        if (pending && bit == lb) {
+            if (lane == leader) atomicOr(&present[lb >> 5], 1u << (lb & 31));
+            pending = false;
+        }
     }
 }
 
