@@ -69,10 +69,11 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     return x;
 }
 
-// Primitive boxes, plus the scene-wide bounds, reduced over each wave first
-// so that one lane per wave updates the shared record (13 words that every
-// primitive would otherwise hit with an atomic).  Lanes past the end take
-// part in the reductions with neutral values.
+// Primitive boxes, plus the scene-wide bounds, reduced over each workgroup
+// (lane shuffles, then the four wave results through LDS) so that one thread
+// per workgroup updates the shared record: its 13 words share one cache line,
+// whose atomics the L2 serialises.  Lanes past the end take part in the
+// reductions with neutral values.
 template <int K>
 __global__ void __launch_bounds__(kB)
 k_prim_boxes(const float *__restrict__ V, int64_t nV, const int32_t *__restrict__ ids, int64_t n,
@@ -112,7 +113,28 @@ k_prim_boxes(const float *__restrict__ V, int64_t nV, const int32_t *__restrict_
         bmx[a] = wave_max_u32(bmx[a]);
     }
     dmx = wave_max_u32(dmx);
+    constexpr int kW = kB / 64;
+    __shared__ uint32_t part[13][kW];
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        for (int a = 0; a < 3; ++a) {
+            part[a][w] = cmn[a];
+            part[3 + a][w] = cmx[a];
+            part[6 + a][w] = bmn[a];
+            part[9 + a][w] = bmx[a];
+        }
+        part[12][w] = dmx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kW; ++k)
+            for (int a = 0; a < 3; ++a) {
+                cmn[a] = min(cmn[a], part[a][k]);
+                cmx[a] = max(cmx[a], part[3 + a][k]);
+                bmn[a] = min(bmn[a], part[6 + a][k]);
+                bmx[a] = max(bmx[a], part[9 + a][k]);
+            }
+        for (int k = 1; k < kW; ++k) dmx = max(dmx, part[12][k]);
         for (int a = 0; a < 3; ++a) {
             atomicMin(&red->cmin[a], cmn[a]);
             atomicMax(&red->cmax[a], cmx[a]);
