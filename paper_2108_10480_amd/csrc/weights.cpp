@@ -214,9 +214,29 @@ void triangle_bernstein(int v, int e, float out[36]) {
 double triangle_weight_min_f64(int v, int e) {
     ensure_basis();
     if (v <= 1) return 1.0;
-    const int n = 512;
+    // coefficients of w~ for (v, e), formed once; Horner in y inside Horner in x
+    double c[8][8] = {};
+    {
+        const double cv = 1.0 / v, ce = 1.0 / e, cc = (v - 1.0) / v;
+        for (int a = 0; a <= 7; ++a)
+            for (int b = 0; a + b <= 7; ++b) {
+                const int k = a * 8 + b;
+                c[a][b] = cv * g_basis[0][k] + ce * g_basis[1][k] + cc * g_basis[2][k];
+            }
+    }
+    auto eval_w = [&c](int, int, double x, double y) {
+        double w = 0;
+        for (int a = 7; a >= 0; --a) {
+            double r = 0;
+            for (int b = 7 - a; b >= 0; --b) r = r * y + c[a][b];
+            w = w * x + r;
+        }
+        return w;
+    };
+    const int n = 256;
     struct Cand { double w, x, y; };
     std::vector<Cand> best;
+    best.reserve((n + 1) * (n + 2) / 2);
     for (int i = 0; i <= n; ++i)
         for (int j = 0; i + j <= n; ++j) {
             double x = double(i) / n, y = double(j) / n;
