@@ -228,9 +228,16 @@ __global__ void __launch_bounds__(kB)
 k_refit(const float4 *__restrict__ plo, const float4 *__restrict__ phi,
         const uint32_t *__restrict__ order, int64_t n, const int32_t *__restrict__ left,
         const int32_t *__restrict__ right, const int32_t *__restrict__ parent,
+        const int32_t *__restrict__ first, const int32_t *__restrict__ last,
         uint32_t *__restrict__ flag, float4 *nlo, float4 *nhi) {
     int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (k >= n) return;
+    // leaves [wlo, whi] belong to this workgroup: a node whose leaf range lies
+    // inside it is reached only by this workgroup's threads, so its counter
+    // orders their box writes at workgroup scope; nodes spanning several
+    // workgroups need agent scope (the L2 write-back and invalidation that
+    // makes the boxes visible across XCDs)
+    const int64_t wlo = (int64_t)blockIdx.x * kB, whi = wlo + kB - 1;
     int64_t node = n - 1 + k;
     uint32_t p = order[k];
     nlo[node] = plo[p];
@@ -238,8 +245,11 @@ k_refit(const float4 *__restrict__ plo, const float4 *__restrict__ phi,
     if (n == 1) return;
     int32_t cur = parent[node];
     while (cur >= 0) {
-        uint32_t old = __hip_atomic_fetch_add(&flag[cur], 1u, __ATOMIC_ACQ_REL,
-                                              __HIP_MEMORY_SCOPE_AGENT);
+        const bool local = first[cur] >= wlo && last[cur] <= whi;
+        uint32_t old = local ? __hip_atomic_fetch_add(&flag[cur], 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP)
+                             : __hip_atomic_fetch_add(&flag[cur], 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
         if (old == 0) return;   // the sibling subtree is not finished yet
         float4 al = nlo[left[cur]], ah = nhi[left[cur]];
         float4 bl = nlo[right[cur]], bh = nhi[right[cur]];
@@ -481,7 +491,7 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
         hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1)), dim3(kB), 0, s, keys, n, left, right,
                            first, last, parent);
     hipLaunchKernelGGL(k_refit, dim3(grid_for(n)), dim3(kB), 0, s, plo, phi, vals, n, left, right,
-                       parent, flag, blo, bhi);
+                       parent, first, last, flag, blo, bhi);
     int64_t acc = 0;
     SD_TRY(dalloc(&sc->lo[cls], 2 * nn, s, &acc));
     sc->hi[cls] = sc->lo[cls] + 1;
