@@ -186,6 +186,39 @@ def test_deterministic(case):
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
+def test_concurrent_threads_and_streams(case):
+    """One scene evaluated from two host threads at once, each on a stream of
+    its own (the scene is read-only after the build; every call allocates its
+    own scratch stream-ordered): every result equals the sequential one bit
+    for bit."""
+    import threading
+    name, sc, scene, _, _ = case
+    Qs = [cuda(_queries(sc, 7000 + 1000 * k, seed=30 + k)) for k in range(2)]
+    ref = [api.sd_eval_grad(scene, Q, 50.0, 0.5) for Q in Qs]
+    torch.cuda.synchronize()
+    out, errors = [None, None], []
+
+    def work(k):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                res = [api.sd_eval_grad(scene, Qs[k], 50.0, 0.5) for _ in range(4)]
+            st.synchronize()
+            out[k] = res
+        except Exception as exc:   # reported below, in the test's own thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for k in range(2):
+        for d, g in out[k]:
+            assert torch.equal(d, ref[k][0]) and torch.equal(g, ref[k][1])
+
+
 def test_value_only_equals_value_of_grad(case):
     name, sc, scene, _, _ = case
     Q = cuda(_queries(sc, 3000, seed=17))
