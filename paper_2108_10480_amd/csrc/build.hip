@@ -463,16 +463,17 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
     uint64_t *keys, *keys2;
     uint32_t *vals, *vals2, *flag;
     int32_t *left, *right, *first, *last, *parent;
-    void *temp;
+    char *temp;
     size_t tb = radix_sort_temp_bytes(n);
-    SD_TRY(dalloc(&plo, n, s)); SD_TRY(dalloc(&phi, n, s));
-    SD_TRY(dalloc(&blo, nn, s)); SD_TRY(dalloc(&bhi, nn, s));
-    SD_TRY(dalloc(&keys, n, s)); SD_TRY(dalloc(&keys2, n, s));
-    SD_TRY(dalloc(&vals, n, s)); SD_TRY(dalloc(&vals2, n, s));
-    SD_TRY(dalloc(&flag, nn, s));
-    SD_TRY(dalloc(&left, nn, s)); SD_TRY(dalloc(&right, nn, s));
-    SD_TRY(dalloc(&first, nn, s)); SD_TRY(dalloc(&last, nn, s)); SD_TRY(dalloc(&parent, nn, s));
-    SD_TRY(dalloc((char **)&temp, (int64_t)tb, s));
+    AsyncScratch tmp(s);
+    SD_TRY(tmp.alloc(&plo, n)); SD_TRY(tmp.alloc(&phi, n));
+    SD_TRY(tmp.alloc(&blo, nn)); SD_TRY(tmp.alloc(&bhi, nn));
+    SD_TRY(tmp.alloc(&keys, n)); SD_TRY(tmp.alloc(&keys2, n));
+    SD_TRY(tmp.alloc(&vals, n)); SD_TRY(tmp.alloc(&vals2, n));
+    SD_TRY(tmp.alloc(&flag, nn));
+    SD_TRY(tmp.alloc(&left, nn)); SD_TRY(tmp.alloc(&right, nn));
+    SD_TRY(tmp.alloc(&first, nn)); SD_TRY(tmp.alloc(&last, nn)); SD_TRY(tmp.alloc(&parent, nn));
+    SD_TRY(tmp.alloc(&temp, (int64_t)tb));
 
     // reset the reduction record: mins to +max, maxes to 0 (ordered encoding)
     Reduce init;
@@ -504,10 +505,6 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
     SD_HIP(hipGetLastError());
     SD_HIP(hipMemcpyAsync(red_host, red_dev, sizeof(Reduce), hipMemcpyDeviceToHost, s));
     SD_HIP(hipStreamSynchronize(s));
-    for (void *p : {(void *)plo, (void *)phi, (void *)blo, (void *)bhi, (void *)keys, (void *)keys2,
-                    (void *)vals, (void *)vals2, (void *)flag, (void *)left, (void *)right,
-                    (void *)first, (void *)last, (void *)parent, temp})
-        SD_HIP(hipFreeAsync(p, s));
     sc->n[cls] = n;
     sc->n_nodes[cls] = nn;
     sc->device_bytes += acc;
@@ -526,8 +523,9 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
 int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int64_t nP,
                 const int32_t *E, int64_t nE, const int32_t *T, int64_t nT, uint32_t flags,
                 hipStream_t s) {
+    AsyncScratch tmp(s);
     Reduce *red_dev;
-    SD_TRY(dalloc(&red_dev, 1, s));
+    SD_TRY(tmp.alloc(&red_dev, 1));
     Reduce red_host;
     memset(&red_host, 0, sizeof(red_host));
 
@@ -543,7 +541,6 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
     SD_HIP(hipMemcpyAsync(&red_host, red_dev, sizeof(Reduce), hipMemcpyDeviceToHost, s));
     SD_HIP(hipStreamSynchronize(s));
     if (red_host.bad) {
-        hipFreeAsync(red_dev, s);
         const char *what = (red_host.bad & 1u) ? "point" : (red_host.bad & 2u) ? "edge" : "triangle";
         return fail(SD_EINVAL, std::string("sd_build_bvh: ") + what + " index outside [0, nV)");
     }
@@ -555,8 +552,10 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
     if (nE > 0) {
         uint32_t *cnt;
         float *wt;
-        SD_TRY(dalloc(&cnt, nV, s));
+        SD_TRY(tmp.alloc(&cnt, nV));
         SD_TRY(dalloc(&wt, 2 * nE, s));
+        sc->wt[1] = wt;   // owned by the scene from here (freed with it on failure)
+        sc->device_bytes += 2 * nE * sizeof(float);
         SD_HIP(hipMemsetAsync(cnt, 0, nV * sizeof(uint32_t), s));
         red_host.maxv = 0;
         SD_HIP(hipMemcpyAsync(red_dev, &red_host, sizeof(Reduce), hipMemcpyHostToDevice, s));
@@ -567,9 +566,6 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
         SD_HIP(hipStreamSynchronize(s));
         sc->A[1] = (double)std::max<uint32_t>(red_host.maxv, 1u);
         SD_TRY(build_class<2>(sc, 1, V, nV, E, nE, wt, s, red_dev, &red_host));
-        SD_HIP(hipFreeAsync(cnt, s));
-        sc->wt[1] = wt;
-        sc->device_bytes += 2 * nE * sizeof(float);
     }
 
     // triangles: 1/v, 1/e, (v-1)/v (App. C.3); A_T strict or literal
@@ -577,17 +573,19 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
         uint32_t *vcnt, *ecnt, *present, *vals, *vals2;
         uint64_t *keys, *keys2;
         float *wt;
-        void *temp;
+        char *temp;
         int64_t m = 3 * nT;
         const int64_t nbits = 1024 * 1024 / 32;
-        SD_TRY(dalloc(&vcnt, nV, s));
-        SD_TRY(dalloc(&ecnt, m, s));
-        SD_TRY(dalloc(&present, nbits, s));
-        SD_TRY(dalloc(&keys, m, s)); SD_TRY(dalloc(&keys2, m, s));
-        SD_TRY(dalloc(&vals, m, s)); SD_TRY(dalloc(&vals2, m, s));
+        SD_TRY(tmp.alloc(&vcnt, nV));
+        SD_TRY(tmp.alloc(&ecnt, m));
+        SD_TRY(tmp.alloc(&present, nbits));
+        SD_TRY(tmp.alloc(&keys, m)); SD_TRY(tmp.alloc(&keys2, m));
+        SD_TRY(tmp.alloc(&vals, m)); SD_TRY(tmp.alloc(&vals2, m));
         SD_TRY(dalloc(&wt, 3 * nT, s));
+        sc->wt[2] = wt;   // owned by the scene from here (freed with it on failure)
+        sc->device_bytes += 3 * nT * sizeof(float);
         size_t tb = radix_sort_temp_bytes(m);
-        SD_TRY(dalloc((char **)&temp, (int64_t)tb, s));
+        SD_TRY(tmp.alloc(&temp, (int64_t)tb));
         SD_HIP(hipMemsetAsync(vcnt, 0, nV * sizeof(uint32_t), s));
         SD_HIP(hipMemsetAsync(present, 0, nbits * sizeof(uint32_t), s));
         red_host.maxv = 0;
@@ -630,8 +628,8 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
         sc->A[2] = (flags & SD_BUILD_A_PAPER_LITERAL) ? sc->A_T_literal : A;
         memcpy(sc->tri_coef0, table.data(), sizeof(sc->tri_coef0));
         int32_t *lut_dev, *tri_cls;
-        SD_TRY(dalloc(&lut_dev, 1024 * 1024, s));
-        SD_TRY(dalloc(&tri_cls, nT, s));
+        SD_TRY(tmp.alloc(&lut_dev, 1024 * 1024));
+        SD_TRY(tmp.alloc(&tri_cls, nT));
         int64_t acc = 0;
         SD_TRY(dalloc(&sc->tri_table, (int64_t)table.size(), s, &acc));
         sc->device_bytes += acc;
@@ -640,13 +638,7 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
                               hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_tri_class, dim3(grid_for(nT)), dim3(kB), 0, s, wt, nT, lut_dev, tri_cls);
         SD_TRY(build_class<3>(sc, 2, V, nV, T, nT, wt, s, red_dev, &red_host, tri_cls));
-        for (void *p : {(void *)vcnt, (void *)ecnt, (void *)present, (void *)keys, (void *)keys2,
-                        (void *)vals, (void *)vals2, temp, (void *)lut_dev, (void *)tri_cls})
-            SD_HIP(hipFreeAsync(p, s));
-        sc->wt[2] = wt;
-        sc->device_bytes += 3 * nT * sizeof(float);
     }
-    SD_HIP(hipFreeAsync(red_dev, s));
     SD_HIP(hipStreamSynchronize(s));
     return SD_OK;
 }

@@ -1293,12 +1293,13 @@ int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, 
     if (nq <= 0) return SD_OK;
     uint64_t *keys, *keys2;
     uint32_t *vals2;
-    void *temp;
+    char *temp;
     size_t tb = radix_sort_temp_bytes(nq);
-    SD_HIP(hipMallocAsync((void **)&keys, nq * sizeof(uint64_t), s));
-    SD_HIP(hipMallocAsync((void **)&keys2, nq * sizeof(uint64_t), s));
-    SD_HIP(hipMallocAsync((void **)&vals2, nq * sizeof(uint32_t), s));
-    SD_HIP(hipMallocAsync(&temp, tb, s));
+    AsyncScratch tmp(s);
+    SD_TRY(tmp.alloc(&keys, nq));
+    SD_TRY(tmp.alloc(&keys2, nq));
+    SD_TRY(tmp.alloc(&vals2, nq));
+    SD_TRY(tmp.alloc(&temp, (int64_t)tb));
     float ext[3], lo[3];
     for (int a = 0; a < 3; ++a) {
         float e = std::max(sc->box[3 + a] - sc->box[a], 1e-6f);
@@ -1309,7 +1310,6 @@ int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, 
     hipLaunchKernelGGL(k_query_keys, dim3(grid), dim3(kB), 0, s, Q, idx, nq, lo[0], lo[1], lo[2],
                        1.f / ext[0], 1.f / ext[1], 1.f / ext[2], keys, perm);
     SD_TRY(radix_sort_pairs(keys, perm, keys2, vals2, nq, 30, temp, s));
-    for (void *ptr : {(void *)keys, (void *)keys2, (void *)vals2, temp}) SD_HIP(hipFreeAsync(ptr, s));
     return SD_OK;
 }
 
@@ -1406,10 +1406,11 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
         return SD_OK;
     }
     uint32_t *perm = nullptr;
+    AsyncScratch tmp(s);
     if (perm_in) {
         A.perm = perm_in;
     } else if (!(p->flags & SD_NO_QUERY_SORT) && nq >= 4096) {
-        SD_HIP(hipMallocAsync((void **)&perm, nq * sizeof(uint32_t), s));
+        SD_TRY(tmp.alloc(&perm, nq));
         SD_TRY(query_order(sc, Q, nq, perm, s));
         A.perm = perm;
     }
@@ -1422,7 +1423,6 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
         launch_eval<false, false>(A, mask, grid, s);
     }
     SD_HIP(hipGetLastError());
-    if (perm) SD_HIP(hipFreeAsync(perm, s));
     return SD_OK;
 }
 
@@ -1445,9 +1445,10 @@ int evalq_dispatch(const sd_scene *sc, const float *G, int nv, int64_t n, const 
     }
     uint32_t *perm = nullptr;
     float *cen = nullptr;
+    AsyncScratch tmp(s);
     if (!(p->flags & SD_NO_QUERY_SORT) && n >= 4096) {
-        SD_HIP(hipMallocAsync((void **)&cen, n * 3 * sizeof(float), s));
-        SD_HIP(hipMallocAsync((void **)&perm, n * sizeof(uint32_t), s));
+        SD_TRY(tmp.alloc(&cen, n * 3));
+        SD_TRY(tmp.alloc(&perm, n));
         hipLaunchKernelGGL(k_centroids, dim3(grid), dim3(kB), 0, s, G, nv, n, cen);
         SD_TRY(query_order(sc, cen, n, perm, s));
         A.perm = perm;
@@ -1455,8 +1456,6 @@ int evalq_dispatch(const sd_scene *sc, const float *G, int nv, int64_t n, const 
     if (nv == 2) launch_evalq<2>(A, G, mask, grid, s);
     else launch_evalq<3>(A, G, mask, grid, s);
     SD_HIP(hipGetLastError());
-    if (perm) SD_HIP(hipFreeAsync(perm, s));
-    if (cen) SD_HIP(hipFreeAsync(cen, s));
     return SD_OK;
 }
 

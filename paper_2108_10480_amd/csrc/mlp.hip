@@ -1048,16 +1048,15 @@ extern "C" int sd_surrogate_certify(sd_surrogate *h, const float *X, const float
     hipStream_t s = (hipStream_t)stream;
     float *err = nullptr, *part = nullptr;
     const int nblk = 1024;
-    SD_HIP(hipMallocAsync((void **)&err, n * sizeof(float), s));
-    SD_HIP(hipMallocAsync((void **)&part, nblk * sizeof(float), s));
+    AsyncScratch tmp(s);
+    SD_TRY(tmp.alloc(&err, n));
+    SD_TRY(tmp.alloc(&part, nblk));
     SD_TRY(launch_mlp(h, X, n, nullptr, nullptr, nullptr, 0.f, y, err, s));
     hipLaunchKernelGGL(k_max_part, dim3(nblk), dim3(256), 0, s, err, n, part);
     hipLaunchKernelGGL(k_max_part, dim3(1), dim3(256), 0, s, part, (int64_t)nblk, part);
     SD_HIP(hipGetLastError());
     float mx = 0.f;
     SD_HIP(hipMemcpyAsync(&mx, part, sizeof(float), hipMemcpyDeviceToHost, s));
-    SD_HIP(hipFreeAsync(err, s));
-    SD_HIP(hipFreeAsync(part, s));
     SD_HIP(hipStreamSynchronize(s));
     h->eps_cert = safety * mx;
     h->grid = 0;   // a global certificate replaces any local one
@@ -1095,16 +1094,15 @@ extern "C" int sd_surrogate_certify_cells(sd_surrogate *h, const float *X, const
     }
     float *err = nullptr;
     int *bits = nullptr;
-    SD_HIP(hipMallocAsync((void **)&err, n * sizeof(float), s));
-    SD_HIP(hipMallocAsync((void **)&bits, nc * sizeof(int), s));
+    AsyncScratch tmp(s);
+    SD_TRY(tmp.alloc(&err, n));
+    SD_TRY(tmp.alloc(&bits, nc));
     SD_TRY(launch_mlp(h, X, n, nullptr, nullptr, nullptr, 0.f, y, err, s));
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nc)), dim3(256), 0, s, bits, nc, -1);
     hipLaunchKernelGGL(k_cell_max, dim3(blocks(n)), dim3(256), 0, s, X, err, n, A, bits);
     hipLaunchKernelGGL(k_cell_final, dim3(blocks(nc)), dim3(256), 0, s, bits, grid, safety, h->eps_cert,
                        max_margin, h->cell_eps);
     SD_HIP(hipGetLastError());
-    SD_HIP(hipFreeAsync(err, s));
-    SD_HIP(hipFreeAsync(bits, s));
     SD_HIP(hipStreamSynchronize(s));
     h->grid = grid;
     return SD_OK;
@@ -1154,13 +1152,14 @@ extern "C" int sd_eval_surrogate(const sd_scene *sc, const sd_surrogate *h, cons
     hipStream_t s = (hipStream_t)stream;
     uint8_t *flag = routed;
     uint32_t *f32 = nullptr, *pos = nullptr, *idx = nullptr, *ord = nullptr;
-    void *temp = nullptr;
-    if (!flag) SD_HIP(hipMallocAsync((void **)&flag, nQ, s));
+    char *temp = nullptr;
+    AsyncScratch tmp(s);
+    if (!flag) SD_TRY(tmp.alloc(&flag, nQ));
     SD_TRY(launch_mlp(h, Q, nQ, d_out, grad_out, flag, band + h->eps_cert, nullptr, nullptr, s, band));
     // compaction of the routed queries (in index order), then Morton order
-    SD_HIP(hipMallocAsync((void **)&f32, nQ * sizeof(uint32_t), s));
-    SD_HIP(hipMallocAsync((void **)&pos, nQ * sizeof(uint32_t), s));
-    SD_HIP(hipMallocAsync(&temp, radix_sort_temp_bytes(nQ), s));
+    SD_TRY(tmp.alloc(&f32, nQ));
+    SD_TRY(tmp.alloc(&pos, nQ));
+    SD_TRY(tmp.alloc(&temp, (int64_t)radix_sort_temp_bytes(nQ)));
     hipLaunchKernelGGL(k_flags_u32, dim3(blocks(nQ)), dim3(256), 0, s, flag, nQ, f32);
     SD_TRY(exclusive_scan_u32(f32, pos, nQ, temp, s));
     uint32_t last_pos = 0;
@@ -1171,20 +1170,17 @@ extern "C" int sd_eval_surrogate(const sd_scene *sc, const sd_surrogate *h, cons
     const int64_t nfb = (int64_t)last_pos + last_flag;
     int rc = SD_OK;
     if (nfb > 0) {
-        SD_HIP(hipMallocAsync((void **)&idx, nfb * sizeof(uint32_t), s));
+        SD_TRY(tmp.alloc(&idx, nfb));
         hipLaunchKernelGGL(k_compact, dim3(blocks(nQ)), dim3(256), 0, s, flag, pos, nQ, idx);
         SD_HIP(hipGetLastError());
         const uint32_t *perm = idx;
         if (!(p->flags & SD_NO_QUERY_SORT) && nfb >= 4096) {
-            SD_HIP(hipMallocAsync((void **)&ord, nfb * sizeof(uint32_t), s));
+            SD_TRY(tmp.alloc(&ord, nfb));
             rc = query_order(sc, Q, nfb, ord, s, idx);
             perm = ord;
         }
         if (!rc) rc = eval_dispatch(sc, Q, perm, nQ, p, d_out, grad_out, nullptr, false, s, nfb);
     }
-    for (void *ptr : {(void *)f32, (void *)pos, (void *)idx, (void *)ord, temp})
-        if (ptr) SD_HIP(hipFreeAsync(ptr, s));
-    if (!routed) SD_HIP(hipFreeAsync(flag, s));
     if (n_fallback_host) *n_fallback_host = nfb;
     return rc;
 }

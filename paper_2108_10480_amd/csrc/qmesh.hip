@@ -170,11 +170,11 @@ extern "C" int sd_query_mesh_lse(const float *d, const float *grad, int64_t K, i
     hipStream_t s = (hipStream_t)stream;
     if (prim && m > 0) {
         int32_t *bad_dev = nullptr, bad = 0;
-        SD_HIP(hipMallocAsync((void **)&bad_dev, sizeof(int32_t), s));
+        sd::AsyncScratch tmp(s);
+        SD_TRY(tmp.alloc(&bad_dev, 1));
         SD_HIP(hipMemcpyAsync(bad_dev, &bad, sizeof(int32_t), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(sd::k_qm_check, dim3(sd::grid1(m)), dim3(sd::kB), 0, s, prim, m, nV, bad_dev);
         SD_HIP(hipMemcpyAsync(&bad, bad_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        SD_HIP(hipFreeAsync(bad_dev, s));
         SD_HIP(hipStreamSynchronize(s));
         if (bad) return sd::fail(SD_EINVAL, "sd_query_mesh_lse: primitive vertex id outside [0, nV) or empty primitive");
     }
@@ -188,7 +188,8 @@ extern "C" int sd_query_mesh_lse(const float *d, const float *grad, int64_t K, i
     const int64_t C = (m + sd::kChunk - 1) / sd::kChunk;
     char *scratch = nullptr;
     const size_t bytes = (size_t)K * C * (sizeof(float) + sizeof(double)) + (size_t)K * 2 * sizeof(double);
-    SD_HIP(hipMallocAsync((void **)&scratch, bytes, s));
+    sd::AsyncScratch tmp(s);
+    SD_TRY(tmp.alloc(&scratch, (int64_t)bytes));
     double *psum = (double *)scratch;
     double *ms = psum + K * C;
     float *pmin = (float *)(ms + 2 * K);
@@ -198,7 +199,6 @@ extern "C" int sd_query_mesh_lse(const float *d, const float *grad, int64_t K, i
     if (w || vgrad)
         hipLaunchKernelGGL(sd::k_qm_out, dim3(sd::grid1(K * m)), dim3(sd::kB), 0, s, d, grad, K, m, alpha_q, ms,
                            prim, nV, w, vgrad);
-    SD_HIP(hipFreeAsync(scratch, s));
     SD_HIP(hipGetLastError());
     return SD_OK;
 }

@@ -142,7 +142,8 @@ extern "C" int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64
     size_t bytes = (size_t)K * chunks * 12 * sizeof(float);
     if (want_x) bytes = std::max(bytes, (size_t)kchunks * m * 3 * sizeof(float));
     float *part = nullptr;
-    SD_HIP(hipMallocAsync((void **)&part, bytes, s));
+    sd::AsyncScratch tmp(s);
+    SD_TRY(tmp.alloc(&part, (int64_t)(bytes / sizeof(float))));
     if (m > 0) {
         hipLaunchKernelGGL(sd::k_rigid_rt_part, dim3((unsigned)K, (unsigned)chunks), dim3(256), 0, s, X, m, chunk,
                            gbar, grad, part);
@@ -158,7 +159,6 @@ extern "C" int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64
         hipLaunchKernelGGL(sd::k_rigid_x_final, dim3((unsigned)((3 * m + 255) / 256)), dim3(256), 0, s, part, m,
                            kchunks, Xbar);
     }
-    SD_HIP(hipFreeAsync(part, s));
     SD_HIP(hipGetLastError());
     return SD_OK;
 }

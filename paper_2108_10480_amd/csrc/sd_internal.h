@@ -28,6 +28,41 @@ int fail(int code, const std::string &msg);
         if (_rc != SD_OK) return _rc;       \
     } while (0)
 
+// Stream-ordered scratch of one call: every allocation made through it is
+// released with hipFreeAsync on the same stream when it goes out of scope,
+// after the work enqueued before that point, on the normal path and on every
+// early error return alike.
+class AsyncScratch {
+  public:
+    explicit AsyncScratch(hipStream_t s) : s_(s) {}
+    AsyncScratch(const AsyncScratch &) = delete;
+    AsyncScratch &operator=(const AsyncScratch &) = delete;
+    ~AsyncScratch() {
+        for (size_t k = n_; k-- > 0;) (void)hipFreeAsync(ptr_[k], s_);
+    }
+    // count elements of T (at least one); SD_ENOMEM / SD_EHIP on failure
+    template <class T>
+    int alloc(T **p, int64_t count) {
+        *p = nullptr;
+        if (n_ == kMax) return fail(SD_EHIP, "AsyncScratch: too many buffers");
+        size_t bytes = (size_t)(count > 1 ? count : 1) * sizeof(T);
+        hipError_t e = hipMallocAsync((void **)p, bytes, s_);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            return fail(e == hipErrorOutOfMemory ? SD_ENOMEM : SD_EHIP,
+                        std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        }
+        ptr_[n_++] = (void *)*p;
+        return SD_OK;
+    }
+
+  private:
+    static constexpr size_t kMax = 24;
+    hipStream_t s_;
+    void *ptr_[kMax] = {};
+    size_t n_ = 0;
+};
+
 // ---------------------------------------------------------------------------
 // Device layout of one class hierarchy (depth-first order, escape indices).
 //
