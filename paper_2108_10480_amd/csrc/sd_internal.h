@@ -74,7 +74,8 @@ class AsyncScratch {
 //   child's escape index.
 //
 // Leaf records (leaf slot k = k-th leaf in depth-first order):
-//   points:    none (the leaf box is the point)
+//   points:    1 x float4 (p.xyz, 1) for the all-pairs kernel; the traversal
+//              takes the point from its leaf's box
 //   edges:     2 x float4 (v0.xyz, 1/N0), (v1.xyz, 1/N1)
 //   triangles: 3 x float4 (v0.xyz, iv), (v1.xyz, ie), (v2.xyz, ic)
 // ---------------------------------------------------------------------------
