@@ -401,6 +401,7 @@ def contact_leg(args, np, torch, api, scenes):
                         f"{sc.counts()[2]} triangles); body of {len(body_v)} vertices dropped from 1 m, "
                         f"alpha=alpha_q=50, d_safe=0.05, h=0.01, {nsteps} steps from 0.3 m above the scene under it",
             "ms_per_step": dt / nsteps * 1e3, "ipm_iterations_mean": float(np.mean(iters)),
+            "solves_ended_without_feasible_step": step.stalls,
             "constraint_evaluations": evals, "ms_per_evaluation": dt / evals * 1e3,
             "start_height_above_ground": float(start[2] - ground), "final_height_above_ground": float(body.p[2] - ground),
             "final_speed": float(np.linalg.norm(body.v))}

@@ -76,6 +76,7 @@ class ContactStep:
         self.d_safe, self.h, self.g = d_safe, h, np.asarray(gravity, np.float64)
         self.max_iter, self.tol = max_iter, tol
         self.evals = 0
+        self.stalls = 0   # solves ended at a feasible iterate with no feasible step left
 
     # constraint c(x) = D - d_safe and its gradient in x = (p, theta), theta a
     # rotation vector applied on the left of the step's start orientation R0
@@ -143,11 +144,18 @@ class ContactStep:
             while True:
                 xn = x + a * dx
                 cn, gn = self.constraint(body, xn, R0)
-                if cn > 0:
+                if cn > 0 or a < 1e-12:
                     break
                 a *= 0.5
-                if a < 1e-12:
-                    raise RuntimeError("line search failed to stay feasible")
+            if not cn > 0:
+                # no feasible step along dx: next to the boundary the
+                # Barnes-Hut constraint is only piecewise smooth (the near/far
+                # switch moves it by rounding-sized jumps), so a Newton step
+                # that would bring c closer to 0 can leave the feasible side
+                # however short it is.  The current iterate is feasible and
+                # as close to the optimum as the constraint resolves: end here.
+                self.stalls += 1
+                break
             x, c, gc = xn, cn, gn
             s = c
             lam = max(lam + a_l * dl, 1e-16)
