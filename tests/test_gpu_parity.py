@@ -157,6 +157,14 @@ def test_exported_hierarchy_is_valid(case):
         assert np.all(left[internal] == internal + 1)
         for ch in (left[internal], right[internal]):
             assert np.all(box[ch, :3] >= box[internal, :3]) and np.all(box[ch, 3:] <= box[internal, 3:])
+        # tight: an internal box is exactly the union of its children's boxes
+        # and a leaf box exactly its primitive's box (FP32 min / max are exact)
+        l, r = left[internal], right[internal]
+        assert np.array_equal(box[internal, :3], np.minimum(box[l, :3], box[r, :3]))
+        assert np.array_equal(box[internal, 3:], np.maximum(box[l, 3:], box[r, 3:]))
+        lv = np.where(left < 0)[0]
+        xyz = (osc.Pxyz, osc.Exyz, osc.Txyz)[c].astype(np.float32).reshape(n, c + 1, 3)[prim[lv]]
+        assert np.array_equal(box[lv, :3], xyz.min(1)) and np.array_equal(box[lv, 3:], xyz.max(1))
 
 
 def test_weight_data_matches_oracle_valences(case):
