@@ -55,6 +55,23 @@ def test_full_size_icosphere_in_benchmark_launch(alpha):
     assert np.all(dc[idx] <= dm)           # and against the minimum distance (App. A)
 
 
+def test_full_size_hierarchy_is_tight():
+    """The level-7 hierarchy (655,359 nodes over 1,280 workgroups of leaves):
+    every internal box is exactly the union of its children's boxes and
+    every leaf box exactly its triangle's box, so the bottom-up refit saw
+    every child box it combined."""
+    require_gpu()
+    w = _workload()
+    box, left, right, prim = api.sd_export_bvh(w["scene"], 2)
+    internal = np.where(left >= 0)[0]
+    l, r = left[internal], right[internal]
+    assert np.array_equal(box[internal, :3], np.minimum(box[l, :3], box[r, :3]))
+    assert np.array_equal(box[internal, 3:], np.maximum(box[l, 3:], box[r, 3:]))
+    lv = np.where(left < 0)[0]
+    tri = w["sc"].V[w["sc"].T[prim[lv]]]
+    assert np.array_equal(box[lv, :3], tri.min(1)) and np.array_equal(box[lv, 3:], tri.max(1))
+
+
 def test_full_size_street_rigid_step_in_benchmark_launch():
     """The rigid-body street workload at full size (2M points, 20,000 wire
     segments, the 50,000-triangle torus at rest; 256 placements of the
@@ -117,6 +134,13 @@ def test_full_size_terrain_alpha_and_precision_modes():
     Qd = cuda(Q)
     perm = api.sd_query_order(scene, Qd)
     osc, trees, floor = oracle_scene(sc), oracle_trees(scene), floor_of(sc)
+    for c in range(3):   # tight hierarchies at this size (40M nodes for the points)
+        box, left, right, _ = api.sd_export_bvh(scene, c)
+        internal = np.where(left >= 0)[0]
+        l, r = left[internal], right[internal]
+        assert np.array_equal(box[internal, :3], np.minimum(box[l, :3], box[r, :3]))
+        assert np.array_equal(box[internal, 3:], np.maximum(box[l, 3:], box[r, 3:]))
+        del box, left, right, internal, l, r
     idx = np.sort(np.random.default_rng(9).choice(nq, 500, replace=False))
     Qs = Q[idx].astype(np.float64)
     dm = O.dmin(osc, Qs)
