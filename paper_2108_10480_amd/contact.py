@@ -64,7 +64,14 @@ class RigidBody:
         self.R = np.eye(3) if R is None else np.asarray(R, np.float64)
         self.v = np.asarray(v, np.float64) + 0.0
         self.omega = np.asarray(omega, np.float64) + 0.0
-        self.Xd = torch.as_tensor(self.X, device="cuda")
+        self._Xd = None
+
+    @property
+    def Xd(self):
+        """The body-frame vertices in device memory (copied on first use)."""
+        if self._Xd is None:
+            self._Xd = torch.as_tensor(self.X, device="cuda")
+        return self._Xd
 
 
 class ContactStep:
