@@ -559,7 +559,7 @@ def sweep_leg(args, np, torch, api, scenes):
                 res["dmin"] = O.dmin(osc, Qh)
             dr, _, st = O.barnes_hut(osc, trees, Qh, alpha, beta, cut_f32=True)
             for mode, (dn, dc) in row.pop("_gpu").items():
-                e = O.value_error(dn, dr, floor, res["dmin"])
+                e = O.value_error(dn, dr, floor)
                 row[mode]["max_err_vs_oracle"] = float(e.max())
                 row[mode]["median_err_vs_oracle"] = float(np.median(e))
                 row[mode]["conservative_violations"] = int(np.sum(dc > dr))

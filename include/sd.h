@@ -11,6 +11,12 @@
  * with the paper's blending weights w_i = (A w~_i)^S (Sec. 3.3, App. C) and its
  * conservative Barnes-Hut far field (Sec. 3.5, App. D, Alg. 1, Alg. 2).
  *
+ * Precision: distances, closest points and barycentric coordinates are formed
+ * in FP64 from the FP32 inputs, the weight polynomials evaluated in FP64, the
+ * sums accumulated in FP64 and the result rounded once to FP32; directions,
+ * weight gradients and exponentials are FP32.  Results are conservative,
+ * d <= d_min, unless SD_NO_CONSERVATIVE_ROUNDING is given.
+ *
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers unless the name ends in _host.
  *     Float arrays are FP32, row-major; index arrays are int32.
@@ -51,9 +57,14 @@ enum {
 #define SD_GRAD_PAPER_METRIC 0x1u   /* barycentric gradients in the alpha-scaled metric of Sec. 3.3
                                        (weight-gradient term divided by alpha once more); the
                                        default is the exact derivative of Eq. 3                 */
-#define SD_ROOTLOG_F64       0x2u   /* final logarithm of the accumulated sum in FP64 (Alg. 2)   */
+#define SD_ROOTLOG_F64       0x2u   /* accepted and without effect: the final logarithm of the
+                                       accumulated sum (Alg. 2) is always taken in FP64        */
 #define SD_NO_QUERY_SORT     0x4u   /* evaluate queries in input order (no Morton reordering)    */
-#define SD_NO_CONSERVATIVE_ROUNDING 0x8u /* skip the downward rounding of terms and result     */
+#define SD_NO_CONSERVATIVE_ROUNDING 0x8u /* skip the final clamp that keeps d <= d_min in FP32:
+                                       by default d is lowered to the smallest rigorous lower
+                                       bound of a summed term's distance where it exceeds it
+                                       (App. A, Sec. 3.5: d <= every term distance <= d_min);
+                                       only results within rounding of that bound change     */
 #define SD_NO_PRUNE          0x10u  /* visit every node Alg. 1 visits, even subtrees whose terms
                                        are all below exp(-64) of the running maximum (by default
                                        those are skipped when alpha x scene diagonal > 1000:

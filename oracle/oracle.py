@@ -348,6 +348,23 @@ def dmin(scene: OracleScene, Q):
     return out
 
 
+def dmin_tree(scene: OracleScene, trees, Q):
+    """Eq. 2 by branch and bound over hierarchies whose boxes contain their
+    primitives (``trees`` as for barnes_hut): equal to ``dmin``, at a cost
+    that allows every query of a large workload to be checked."""
+    Q = np.ascontiguousarray(Q, np.float64)
+    out = np.empty(len(Q))
+    s = scene._struct()
+    ts = (_OrTree * 3)()
+    for c in range(3):
+        if trees[c] is None:
+            ts[c].n_nodes = 0
+        else:
+            ts[c] = trees[c]._struct()
+    lib().or_dmin_tree(ctypes.byref(s), ts, ctypes.c_int64(len(Q)), _ptr(Q), _ptr(out))
+    return out
+
+
 def closest(cls, prim, q):
     """Closest point of one primitive (0 point, 1 segment, 2 triangle) to q.
     Returns dict(d, c, phi, dphi, region)."""
@@ -481,17 +498,11 @@ def rigid_adjoint(X, R, gbar, grad):
 # --------------------------------------------------------------------------
 # Error measures used by the parity tests
 # --------------------------------------------------------------------------
-def value_error(d, d_ref, floor, dmin=None):
-    """|d - d_ref| / max(|d_ref|, d_min, floor).
-
-    Relative error measured against the magnitudes the log-sum-exp combines:
-    the result d = d* - log(sum)/alpha cancels two terms of size up to the
-    nearest distance d_min where it crosses zero, so d_min (when given) joins
-    |d_ref| in the denominator; ``floor`` (1e-3 of the scene diagonal in the
-    tests) covers queries on the data itself."""
+def value_error(d, d_ref, floor):
+    """|d - d_ref| / max(|d_ref|, floor): the relative error of the value,
+    with an absolute floor (1e-3 of the scene diagonal in the tests) where the
+    reference crosses zero, i.e. near the zero isosurface and on the data."""
     den = np.maximum(np.abs(d_ref), floor)
-    if dmin is not None:
-        den = np.maximum(den, np.asarray(dmin, np.float64))
     return np.abs(np.asarray(d, np.float64) - d_ref) / den
 
 

@@ -308,6 +308,57 @@ int or_dmin(const or_scene *sc, int64_t nq, const double *Q, double *dmin_out) {
     return 0;
 }
 
+/* Eq. 2 by branch and bound over given hierarchies (every box contains its
+ * primitives): a node is skipped only when the distance from q to its box,
+ * which no primitive inside can undercut, is at least the best distance found
+ * so far, so the result equals the brute-force minimum.  For the
+ * conservativeness checks on large query sets. */
+typedef struct { const or_scene *sc; const or_tree *tr; int cls; v3 q; double best; } nn_ctx;
+
+static double prim_distance(const or_scene *sc, int cls, int64_t i, v3 q) {
+    closest cp;
+    if (cls == 0) point_closest(q, ld(sc->P + 3 * i), &cp);
+    else if (cls == 1) segment_closest(q, ld(sc->E + 6 * i), ld(sc->E + 6 * i + 3), &cp);
+    else triangle_closest(q, ld(sc->T + 9 * i), ld(sc->T + 9 * i + 3), ld(sc->T + 9 * i + 6), &cp);
+    return cp.d;
+}
+
+static double box_distance(const float *b, v3 q) {
+    v3 y = mk(fmin(fmax(q.x, b[0]), b[3]), fmin(fmax(q.y, b[1]), b[4]), fmin(fmax(q.z, b[2]), b[5]));
+    return norm(sub(q, y));
+}
+
+static void nearest(nn_ctx *cx, int32_t node) {
+    if (box_distance(cx->tr->box + 6 * (int64_t)node, cx->q) >= cx->best) return;
+    if (cx->tr->left[node] < 0) {
+        double d = prim_distance(cx->sc, cx->cls, cx->tr->prim[node], cx->q);
+        if (d < cx->best) cx->best = d;
+        return;
+    }
+    int32_t a = cx->tr->left[node], b = cx->tr->right[node];
+    /* nearer child first, so the bound tightens early */
+    if (box_distance(cx->tr->box + 6 * (int64_t)b, cx->q) < box_distance(cx->tr->box + 6 * (int64_t)a, cx->q)) {
+        int32_t t = a; a = b; b = t;
+    }
+    nearest(cx, a);
+    nearest(cx, b);
+}
+
+int or_dmin_tree(const or_scene *sc, const or_tree *trees, int64_t nq, const double *Q, double *dmin_out) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < nq; ++k) {
+        nn_ctx cx;
+        cx.sc = sc; cx.q = ldd(Q + 3 * k); cx.best = INFINITY;
+        for (int c = 0; c < 3; ++c) {
+            if (trees[c].n_nodes <= 0) continue;
+            cx.cls = c; cx.tr = &trees[c];
+            nearest(&cx, 0);
+        }
+        dmin_out[k] = cx.best;
+    }
+    return 0;
+}
+
 /* Single primitive closest-point query, exposed for the pin tests. */
 int or_closest(int cls, const float *prim, const double *q, double *out /* d, c[3], phi[2], dphi[6], region */) {
     closest cp;

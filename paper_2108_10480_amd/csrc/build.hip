@@ -259,13 +259,8 @@ k_refit(const float4 *__restrict__ plo, const float4 *__restrict__ phi,
     }
 }
 
-// float log(count) rounded up from FP64 (proxy weights stay conservative)
-__device__ inline float log_count_up(int64_t c) {
-    double v = log((double)c);
-    float f = (float)v;
-    if ((double)f < v) f = __int_as_float(__float_as_int(f) + 1);
-    return f;
-}
+// log(count) from FP64, rounded to the nearest float
+__device__ inline float log_count(int64_t c) { return (float)log((double)c); }
 
 __global__ void __launch_bounds__(kB)
 k_dfs_layout(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ first,
@@ -291,7 +286,7 @@ k_dfs_layout(int64_t n, const int32_t *__restrict__ left, const int32_t *__restr
     int32_t esc32 = esc >= total ? -1 : (int32_t)esc;
     float4 a = blo[x], b = bhi[x];
     a.w = __int_as_float(esc32);
-    b.w = leaf ? __int_as_float((int32_t)(0x80000000u | (uint32_t)l)) : log_count_up(cnt);
+    b.w = leaf ? __int_as_float((int32_t)(0x80000000u | (uint32_t)l)) : log_count(cnt);
     out_lo[2 * pos] = a;   // records interleaved: lo, hi of a node share a cache line
     out_hi[2 * pos] = b;
 }
@@ -607,14 +602,18 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
         sc->A_T_literal = A;
         int ncls = 0;
         std::vector<int32_t> lut(1024 * 1024, 0);
-        std::vector<float> table;
+        std::vector<double> table;
         for (int64_t b = 0; b < nbits * 32; ++b) {
             if (!((pres[b >> 5] >> (b & 31)) & 1u)) continue;
             int v = (int)(b / 1024), e = (int)(b % 1024);
             lut[b] = ncls++;
+            double mono[36];
+            triangle_monomial_horner(v, e, mono);
+            table.insert(table.end(), mono, mono + 36);
+            // the largest Bernstein coefficient bounds w~ from above (convex hull)
             float bern[36];
             triangle_bernstein(v, e, bern);
-            table.insert(table.end(), bern, bern + 36);
+            for (float c : bern) sc->tri_wmax = std::max(sc->tri_wmax, (double)c);
             if (v <= 1) continue;
             double wmin = triangle_weight_min_f64(v, e);
             if (!(wmin > 0))
@@ -624,9 +623,8 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
             A = std::max(A, 1.0 / wmin);
         }
         sc->n_tri_classes = ncls;
-        for (float b : table) sc->tri_wmax = std::max(sc->tri_wmax, (double)b);
         sc->A[2] = (flags & SD_BUILD_A_PAPER_LITERAL) ? sc->A_T_literal : A;
-        memcpy(sc->tri_coef0, table.data(), sizeof(sc->tri_coef0));
+        memcpy(sc->tri_mono0, table.data(), sizeof(sc->tri_mono0));
         int32_t *lut_dev, *tri_cls;
         SD_TRY(tmp.alloc(&lut_dev, 1024 * 1024));
         SD_TRY(tmp.alloc(&tri_cls, nT));
@@ -634,7 +632,7 @@ int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int6
         SD_TRY(dalloc(&sc->tri_table, (int64_t)table.size(), s, &acc));
         sc->device_bytes += acc;
         SD_HIP(hipMemcpyAsync(lut_dev, lut.data(), lut.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        SD_HIP(hipMemcpyAsync(sc->tri_table, table.data(), table.size() * sizeof(float),
+        SD_HIP(hipMemcpyAsync(sc->tri_table, table.data(), table.size() * sizeof(double),
                               hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_tri_class, dim3(grid_for(nT)), dim3(kB), 0, s, wt, nT, lut_dev, tri_cls);
         SD_TRY(build_class<3>(sc, 2, V, nV, T, nT, wt, s, red_dev, &red_host, tri_cls));

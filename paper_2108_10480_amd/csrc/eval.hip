@@ -8,13 +8,28 @@
 //   k_brute    the same leaf terms over every primitive, primitives staged
 //              through LDS in tiles (beta = 0 semantics).
 //
-// Online log-sum-exp state per lane: the distance d* and log-weight l* of the
-// largest term so far, the sum s of exp(L_i - L*) and the gradient numerator
-// G, both accumulated in FP64 (the terms are FP32; an FP64 add or FMA issues at
-// the rate of an FP32 one on this GPU, so this is cheaper than compensated
-// FP32 sums and more accurate).  Exponents are formed as
-// alpha (d* - d_i) + (l_i - l*), so large alpha d never overflows and no
-// precision is lost to the magnitude of alpha d.  d = d* - (l* + log s)/alpha.
+// Precision.  Every term enters the log-sum-exp through its log-term
+// L_i = log w_i - alpha d_i, and an error e in d_i changes the term's weight by
+// the factor exp(alpha e): with FP32 distances (e ~ 2^-23 d) that is 3e-5 at
+// alpha = 500, d = 1, which shows in the gradient.  So distances, closest
+// points and barycentric coordinates are formed in FP64 from the FP32 inputs
+// (differences of FP32 values are exact in FP64), and the triangle weight
+// polynomial is evaluated in FP64 (monomial Horner form): an FP64 FMA issues
+// at the rate of an FP32 one on this GPU, so this costs registers rather than
+// issue slots.  Directions, weight gradients and exponentials stay FP32.
+//
+// Online log-sum-exp state per lane: the largest log-term L* so far (FP64), the
+// sum s of exp(L_i - L*) and the gradient numerator G (FP64 sums of FP32
+// terms).  d = -(L* + log s) / alpha, formed in FP64 and rounded once.
+//
+// Conservativeness (App. A, Sec. 3.5).  With every weight >= 1 the exact
+// log-sum-exp is at most the smallest term distance, which is at most the
+// exact minimum distance d_min (each far-field box distance D_B is below the
+// distances of its primitives).  Each term also carries a rigorous lower bound
+// of its exact distance; by default the result is clamped to the smallest of
+// these, so d <= d_min holds for the FP32 output whatever the rounding, and
+// the clamp changes the result only where it is within rounding of that
+// smallest term distance.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -39,6 +54,9 @@ __device__ __forceinline__ float dop(float a, float b, float c, float d) {
 __device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz) {
     return fmaf(ax, bx, fmaf(ay, by, az * bz));
 }
+__device__ __forceinline__ double ddot3(double ax, double ay, double az, double bx, double by, double bz) {
+    return fma(ax, bx, fma(ay, by, az * bz));
+}
 
 // Hardware square root and reciprocal (1 ulp) instead of the correctly rounded
 // multi-instruction sequences; the error bounds below allow for them.
@@ -46,20 +64,44 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fdiv(float a, float b) { return a * frcp(b); }
 
-struct LSE {
-    float dref, lref;
-    double s, gx, gy, gz;
-};
-
-// clamp(q, lo, hi) in one v_med3_f32 (lo <= hi for every box)
-__device__ __forceinline__ float clampf(float q, float lo, float hi) {
-    return __builtin_amdgcn_fmed3f(q, lo, hi);
+// The distance sqrt(s) in FP64 from its FP64 square s and an FP32 estimate r
+// within a few ulps of it (inv_r = 1/r): one Newton step r + (s - r^2) / (2 r)
+// leaves a relative error near 2^-46.  r = 0 gives 0.
+__device__ __forceinline__ double sqrt_newton(double s, float r, float inv_r) {
+    const double rr = (double)r;
+    const float e = (float)fma(-rr, rr, s);
+    return r > 0.f ? rr + (double)(e * (0.5f * inv_r)) : 0.0;
 }
 
+// Lower-bound factor of an FP32 distance formed from rounded FP32 differences,
+// a sum of squares by FMA and the hardware square root (at most about 2^-21.8
+// relative error): d (1 - 2^-21) is below the exact distance.
+constexpr float kLo = 1.f - 0x1p-21f;
+// Lower bound of an edge or triangle distance r (FP32 square root of the FP64
+// square s): the closest point q - c is formed in FP64 from exact differences
+// with its parameters clamped to the primitive, so sqrt(s) falls short of the
+// exact distance by at most a few FP64 roundings of the vectors involved
+// (o1 bounds their 1-norms); 2^-40 o1 covers that with a wide margin.
+__device__ __forceinline__ float dist_lo(float r, float o1) { return fmaf(-0x1p-40f, o1, r * kLo); }
+
+struct LSE {
+    double L;                // largest log-term so far (-inf: none yet)
+    double s, gx, gy, gz;    // sum of exp(L_i - L*) and the gradient numerator
+    float Lf;                // L* rounded to FP32 (pruning bound)
+    float mlo;               // lower bound of the smallest term distance
+};
+
+__device__ __forceinline__ void lse_init(LSE &st) {
+    st.L = -INFINITY;
+    st.s = st.gx = st.gy = st.gz = 0.0;
+    st.Lf = -INFINITY;
+    st.mlo = INFINITY;
+}
+
+// Fold one term with exponent t = L_i - L* (FP32); Lnew is the term's log-term
+// in FP64, which becomes the reference when t > 0.
 template <bool GRAD>
-__device__ __forceinline__ void lse_add(LSE &st, float d, float lw, float gx, float gy, float gz,
-                                        float alpha) {
-    float t = fmaf(alpha, st.dref - d, lw - st.lref);   // L_i - L*
+__device__ __forceinline__ void lse_fold(LSE &st, float t, double Lnew, float gx, float gy, float gz) {
     if (t <= 0.f) {
         double e = (double)__expf(t);
         st.s += e;
@@ -76,91 +118,101 @@ __device__ __forceinline__ void lse_add(LSE &st, float d, float lw, float gx, fl
             st.gy = fma(st.gy, e, (double)gy);
             st.gz = fma(st.gz, e, (double)gz);
         }
-        st.dref = d;
-        st.lref = lw;
+        st.L = Lnew;
+        st.Lf = (float)Lnew;
     }
 }
 
+// One term: log-term L (FP64), lower bound dlo of its distance, and g = grad d -
+// grad(log w)/alpha (the Eq. 4 numerator direction).
+template <bool GRAD>
+__device__ __forceinline__ void lse_add(LSE &st, double L, float dlo, float gx, float gy, float gz) {
+    st.mlo = fminf(st.mlo, dlo);
+    lse_fold<GRAD>(st, (float)(L - st.L), L, gx, gy, gz);
+}
+
+// clamp(q, lo, hi) in one v_med3_f32 (lo <= hi for every box)
+__device__ __forceinline__ float clampf(float q, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(q, lo, hi);
+}
+
 // ---------------------------------------------------------------------------
-// Triangle weight polynomial (App. C.3) in degree-7 Bernstein-Bezier form on
-// the barycentric triangle: w~ = sum_{i+j+k=7} b_ijk 7!/(i!j!k!) l0^i l1^j l2^k
-// with l1 = phi1, l2 = phi2, l0 = 1 - phi1 - phi2.  The basis is non-negative
-// and sums to one there, so FP32 evaluation stays within a few ulps.
-// Derivatives: d/dphi1 = 7 sum_{|m|=6} (b_{m+e1} - b_{m+e0}) B^6_m, likewise phi2.
+// Triangle weight polynomial (App. C.3): w~ = sum_{a+b<=7} c_ab phi1^a phi2^b
+// in FP64, Horner in phi1 outside and in phi2 inside, with both partial
+// derivatives carried along.  The monomial form cancels by up to ~500x, which
+// FP64 absorbs (~1e-13 relative).  Coefficient k runs over a = 7 .. 0 and,
+// for each a, b = 7 - a .. 0.
 // ---------------------------------------------------------------------------
 struct Poly2 {
-    float w, wx, wy;
+    double w, wx, wy;
 };
 
-__host__ __device__ constexpr int bidx(int j, int k) { return j * 8 - (j * (j - 1)) / 2 + k; }
-
-// de Casteljau on the barycentric triangle: each level replaces the points of
-// degree n by convex combinations l0 c(i+1,j,k) + l1 c(i,j+1,k) + l2 c(i,j,k+1)
-// in place (slot (j, k), i implied).  The three degree-1 points give the value
-// and both partial derivatives: w_phi1 = 7 (c1 - c0), w_phi2 = 7 (c2 - c0).
 template <class Coef>
-__device__ __forceinline__ Poly2 tri_weight(const Coef &coef, float x, float y) {
-    float c[36];
-    coef.load(c);
-    const float l0 = 1.f - x - y;
+__device__ __forceinline__ Poly2 tri_weight(const Coef &coef, double x, double y) {
+    double w = 0.0, wx = 0.0, wy = 0.0;
+    int k = 0;
 #pragma unroll
-    for (int n = 7; n >= 2; --n) {
+    for (int a = 7; a >= 0; --a) {
+        double p = coef(k++), dp = 0.0;   // P_a(y) = sum_b c_ab y^b and P_a'(y)
 #pragma unroll
-        for (int j = 0; j <= n - 1; ++j) {
-#pragma unroll
-            for (int k = 0; j + k <= n - 1; ++k) {
-                c[bidx(j, k)] = fmaf(l0, c[bidx(j, k)], fmaf(x, c[bidx(j + 1, k)], y * c[bidx(j, k + 1)]));
-            }
+        for (int b = 7 - a - 1; b >= 0; --b) {
+            dp = fma(dp, y, p);
+            p = fma(p, y, coef(k++));
         }
+        wx = fma(wx, x, w);
+        w = fma(w, x, p);
+        wy = fma(wy, x, dp);
     }
-    Poly2 r;
-    const float c0 = c[bidx(0, 0)], c1 = c[bidx(1, 0)], c2 = c[bidx(0, 1)];
-    r.w = fmaf(l0, c0, fmaf(x, c1, y * c2));
-    r.wx = 7.f * (c1 - c0);
-    r.wy = 7.f * (c2 - c0);
-    return r;
+    return Poly2{w, wx, wy};
 }
 
 struct CoefUniform {   // single valence class: coefficients in the kernel arguments
     const EvalArgs &A;
-    __device__ __forceinline__ void load(float c[36]) const {
-#pragma unroll
-        for (int t = 0; t < 36; ++t) c[t] = A.tri_coef[t];
-    }
+    __device__ __forceinline__ double operator()(int k) const { return A.tri_mono[k]; }
 };
-struct CoefTable {     // several classes: per-class rows of a device table (16-B aligned)
-    const float *row;
-    __device__ __forceinline__ void load(float c[36]) const {
-        const float4 *r4 = reinterpret_cast<const float4 *>(row);
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            float4 v = r4[t];
-            c[4 * t] = v.x; c[4 * t + 1] = v.y; c[4 * t + 2] = v.z; c[4 * t + 3] = v.w;
+// Several valence classes: the lane's row of the class table, read as the
+// Horner loop consumes it (a rolled loop keeps the row out of the registers).
+__device__ __forceinline__ Poly2 tri_weight_table(const double *__restrict__ row, double x, double y) {
+    double w = 0.0, wx = 0.0, wy = 0.0;
+    int k = 0;
+#pragma unroll 1
+    for (int a = 7; a >= 0; --a) {
+        double p = row[k++], dp = 0.0;
+#pragma unroll 1
+        for (int b = 7 - a - 1; b >= 0; --b) {
+            dp = fma(dp, y, p);
+            p = fma(p, y, row[k++]);
         }
+        wx = fma(wx, x, w);
+        w = fma(w, x, p);
+        wy = fma(wy, x, dp);
     }
-};
+    return Poly2{w, wx, wy};
+}
 
 // ---------------------------------------------------------------------------
-// Exact leaf terms.  Each returns the distance d, log-weight lw and, when
-// GRAD, g = grad d - grad(log w)/alpha (the Eq. 4 numerator direction).
+// Exact leaf terms.  Each returns the distance d (FP64), the log-weight lw,
+// a lower bound dlo of the exact distance and, when GRAD, g = grad d -
+// grad(log w)/alpha.
 // ---------------------------------------------------------------------------
-// err bounds the FP32 rounding of d: the computed difference vectors are
-// exact up to a few ulps of the offset o from the vertex they are formed
-// against, so |d_fp32 - d| <= 2^-21 (d + |o|_1).  With conservative rounding
-// on (the default) each term enters the sum at d - err, so every term, and
-// hence the log-sum-exp, stays an underestimate (App. A) in FP32 too.
 struct Term {
-    float d, lw, gx, gy, gz, err;
+    double d;
+    float lw, dlo, gx, gy, gz;
 };
 
 template <bool GRAD>
 __device__ __forceinline__ Term point_term(float4 p, float qx, float qy, float qz) {
-    float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-    float d = fsqrt(dot3(dx, dy, dz, dx, dy, dz));
-    Term t{d, 0.f, 0.f, 0.f, 0.f, d * 0x1p-21f};
-    if (GRAD && d > 0.f) {
-        float inv = frcp(d);
-        t.gx = dx * inv; t.gy = dy * inv; t.gz = dz * inv;
+    const double ex = (double)qx - (double)p.x, ey = (double)qy - (double)p.y, ez = (double)qz - (double)p.z;
+    const double s = ddot3(ex, ey, ez, ex, ey, ez);
+    const float r = fsqrt((float)s);
+    const float inv = r > 0.f ? frcp(r) : 0.f;
+    Term t;
+    t.d = sqrt_newton(s, r, inv);
+    t.lw = 0.f;
+    t.dlo = r * kLo;
+    t.gx = t.gy = t.gz = 0.f;
+    if (GRAD) {
+        t.gx = (float)ex * inv; t.gy = (float)ey * inv; t.gz = (float)ez * inv;
     }
     return t;
 }
@@ -169,155 +221,157 @@ __device__ __forceinline__ Term point_term(float4 p, float qx, float qy, float q
 template <bool GRAD>
 __device__ __forceinline__ Term edge_term(float4 r0, float4 r1, float qx, float qy, float qz,
                                           float S, float slogA, float inv_alpha, bool metric) {
-    float ex = r1.x - r0.x, ey = r1.y - r0.y, ez = r1.z - r0.z;
-    float px = qx - r0.x, py = qy - r0.y, pz = qz - r0.z;
-    float ee = dot3(ex, ey, ez, ex, ey, ez);
-    float t = ee > 0.f ? fdiv(dot3(px, py, pz, ex, ey, ez), ee) : 0.f;
-    bool interior = t > 0.f && t < 1.f;
-    t = fminf(fmaxf(t, 0.f), 1.f);
-    float cx = fmaf(-t, ex, px), cy = fmaf(-t, ey, py), cz = fmaf(-t, ez, pz);
-    float d = fsqrt(dot3(cx, cy, cz, cx, cy, cz));
-    float a = r0.w, b = r1.w;
-    float u = t * (1.f - t);
-    float bump = 16.f * (1.f - 0.5f * (a + b));
+    const double ex = (double)r1.x - (double)r0.x, ey = (double)r1.y - (double)r0.y,
+                 ez = (double)r1.z - (double)r0.z;
+    const double px = (double)qx - (double)r0.x, py = (double)qy - (double)r0.y,
+                 pz = (double)qz - (double)r0.z;
+    const double ee = ddot3(ex, ey, ez, ex, ey, ez);
+    double t = ee > 0.0 ? ddot3(px, py, pz, ex, ey, ez) / ee : 0.0;
+    const bool interior = t > 0.0 && t < 1.0;
+    t = fmin(fmax(t, 0.0), 1.0);
+    const double cx = fma(-t, ex, px), cy = fma(-t, ey, py), cz = fma(-t, ez, pz);
+    const double s = ddot3(cx, cy, cz, cx, cy, cz);
+    const float r = fsqrt((float)s);
+    const float inv = r > 0.f ? frcp(r) : 0.f;
     // w~ = a + (b - a)(3t^2 - 2t^3) + 16 (1 - (a+b)/2) t^2 (1-t)^2
-    float w = fmaf(b - a, t * t * (3.f - 2.f * t), fmaf(bump, u * u, a));
-    Term r{d, fmaf(S, __logf(w), slogA), 0.f, 0.f, 0.f,
-           (d + fabsf(px) + fabsf(py) + fabsf(pz)) * 0x1p-21f};
+    const double a = r0.w, b = r1.w;
+    const double u = t * (1.0 - t);
+    const double bump = 16.0 * (1.0 - 0.5 * (a + b));
+    const double w = fma(b - a, t * t * (3.0 - 2.0 * t), fma(bump, u * u, a));
+    Term o;
+    o.d = sqrt_newton(s, r, inv);
+    o.lw = fmaf(S, __logf((float)w), slogA);
+    o.dlo = dist_lo(r, (float)(fabs(px) + fabs(py) + fabs(pz) + fabs(ex) + fabs(ey) + fabs(ez)));
+    o.gx = o.gy = o.gz = 0.f;
     if (GRAD) {
-        float inv = d > 0.f ? frcp(d) : 0.f;
-        float gx = cx * inv, gy = cy * inv, gz = cz * inv;
+        float gx = (float)cx * inv, gy = (float)cy * inv, gz = (float)cz * inv;
         if (interior) {
             // dw~/dt = 6 (b - a) t (1 - t) + 2 bump t (1 - t)(1 - 2t)
-            float dw = u * fmaf(6.f, b - a, 2.f * bump * (1.f - 2.f * t));
-            float k = S * dw * frcp(w * ee) * inv_alpha;
+            const float dw = (float)(u * fma(6.0, b - a, 2.0 * bump * (1.0 - 2.0 * t)));
+            float k = S * dw * frcp((float)w * (float)ee) * inv_alpha;
             if (metric) k *= inv_alpha;
-            gx = fmaf(-k, ex, gx); gy = fmaf(-k, ey, gy); gz = fmaf(-k, ez, gz);
+            gx = fmaf(-k, (float)ex, gx); gy = fmaf(-k, (float)ey, gy); gz = fmaf(-k, (float)ez, gz);
         }
-        r.gx = gx; r.gy = gy; r.gz = gz;
+        o.gx = gx; o.gy = gy; o.gz = gz;
     }
-    return r;
-}
-
-// closest point of segment a + t e to p (for the degenerate-triangle fallback)
-__device__ __forceinline__ float seg_param(float px, float py, float pz, float ex, float ey, float ez) {
-    float ee = dot3(ex, ey, ez, ex, ey, ez);
-    float t = ee > 0.f ? fdiv(dot3(px, py, pz, ex, ey, ez), ee) : 0.f;
-    return fminf(fmaxf(t, 0.f), 1.f);
+    return o;
 }
 
 // triangle (v0, v1, v2), barycentric phi1 <-> v1, phi2 <-> v2 (App. B).
 // Region classification after Ericson (Real-Time Collision Detection, 5.1.5)
-// with Kahan's FMA difference of products for the region determinants.
+// in FP64 on the exact edge and offset vectors; the region's barycentric
+// coordinates give the closest point, q - f(phi) = ap - phi1 ab - phi2 ac.
 template <bool GRAD>
 __device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float qx, float qy,
                                          float qz, const EvalArgs &A, float slogA, bool metric) {
     const float S = A.S, inv_alpha = A.inv_alpha;
-    float abx = r1.x - r0.x, aby = r1.y - r0.y, abz = r1.z - r0.z;
-    float acx = r2.x - r0.x, acy = r2.y - r0.y, acz = r2.z - r0.z;
-    float apx = qx - r0.x, apy = qy - r0.y, apz = qz - r0.z;
-    float d1 = dot3(abx, aby, abz, apx, apy, apz);
-    float d2 = dot3(acx, acy, acz, apx, apy, apz);
-    float bpx = qx - r1.x, bpy = qy - r1.y, bpz = qz - r1.z;
-    float d3 = dot3(abx, aby, abz, bpx, bpy, bpz);
-    float d4 = dot3(acx, acy, acz, bpx, bpy, bpz);
-    float cpx = qx - r2.x, cpy = qy - r2.y, cpz = qz - r2.z;
-    float d5 = dot3(abx, aby, abz, cpx, cpy, cpz);
-    float d6 = dot3(acx, acy, acz, cpx, cpy, cpz);
-    float vc = dop(d1, d4, d3, d2);
-    float vb = dop(d5, d2, d1, d6);
-    float va = dop(d3, d6, d5, d4);
+    const double abx = (double)r1.x - (double)r0.x, aby = (double)r1.y - (double)r0.y,
+                 abz = (double)r1.z - (double)r0.z;
+    const double acx = (double)r2.x - (double)r0.x, acy = (double)r2.y - (double)r0.y,
+                 acz = (double)r2.z - (double)r0.z;
+    const double apx = (double)qx - (double)r0.x, apy = (double)qy - (double)r0.y,
+                 apz = (double)qz - (double)r0.z;
+    const double g11 = ddot3(abx, aby, abz, abx, aby, abz), g12 = ddot3(abx, aby, abz, acx, acy, acz),
+                 g22 = ddot3(acx, acy, acz, acx, acy, acz);
+    const double d1 = ddot3(abx, aby, abz, apx, apy, apz), d2 = ddot3(acx, acy, acz, apx, apy, apz);
+    // the same products against bp = ap - ab and cp = ap - ac
+    const double d3 = d1 - g11, d4 = d2 - g12, d5 = d1 - g12, d6 = d2 - g22;
+    const double nx = aby * acz - abz * acy, ny = abz * acx - abx * acz, nz = abx * acy - aby * acx;
+    const double nn = ddot3(nx, ny, nz, nx, ny, nz);
+    const double det = g11 * g22 - g12 * g12;
 
-    // region: 0 face, 1 edge ab, 2 edge ac, 3 edge bc, 4 vertex
+    // region: 0 face, 1 edge ab, 2 edge ac, 3 edge bc, 4 vertex; the edge and
+    // face coordinates are num / den, formed after the branches
     int region;
-    float p1, p2, t = 0.f;
-    float dx, dy, dz;      // q - closest point
-    float ex = 0.f, ey = 0.f, ez = 0.f;   // edge direction for the t gradient
-    float nx = dop(aby, acz, abz, acy), ny = dop(abz, acx, abx, acz), nz = dop(abx, acy, aby, acx);
-    float nn = dot3(nx, ny, nz, nx, ny, nz);
-    bool degenerate = !(nn > 0.f);
-    if (degenerate) {
+    double p1 = 0.0, p2 = 0.0, num = 0.0, num2 = 0.0, den = 1.0, inv_den = 0.0;
+    if (!(nn > 0.0 && det > 0.0)) {
         // zero-area triangle: it is its longest edge (which covers the other
         // two), first of ab, bc, ca on ties, so the barycentrics are unique
-        float bcx = r2.x - r1.x, bcy = r2.y - r1.y, bcz = r2.z - r1.z;
-        float lab = dot3(abx, aby, abz, abx, aby, abz), lbc = dot3(bcx, bcy, bcz, bcx, bcy, bcz);
-        float lac = dot3(acx, acy, acz, acx, acy, acz);
-        if (lab >= lbc && lab >= lac) {
-            t = seg_param(apx, apy, apz, abx, aby, abz);
-            p1 = t; p2 = 0.f; ex = abx; ey = aby; ez = abz;
-            dx = fmaf(-t, abx, apx); dy = fmaf(-t, aby, apy); dz = fmaf(-t, abz, apz);
-            region = (t > 0.f && t < 1.f) ? 1 : 4;
-        } else if (lbc >= lac) {
-            t = seg_param(bpx, bpy, bpz, bcx, bcy, bcz);
-            p1 = 1.f - t; p2 = t; ex = bcx; ey = bcy; ez = bcz;
-            dx = fmaf(-t, bcx, bpx); dy = fmaf(-t, bcy, bpy); dz = fmaf(-t, bcz, bpz);
-            region = (t > 0.f && t < 1.f) ? 3 : 4;
+        const double bcx = acx - abx, bcy = acy - aby, bcz = acz - abz;   // exact: v2 - v1
+        const double lbc = ddot3(bcx, bcy, bcz, bcx, bcy, bcz);
+        if (g11 >= lbc && g11 >= g22) {
+            region = 1; num = d1; den = g11;                       // t along ab
+        } else if (lbc >= g22) {
+            region = 3; num = (d4 - d3); den = lbc;                // t along bc
         } else {
-            t = seg_param(apx, apy, apz, acx, acy, acz);
-            p1 = 0.f; p2 = t; ex = acx; ey = acy; ez = acz;
-            dx = fmaf(-t, acx, apx); dy = fmaf(-t, acy, apy); dz = fmaf(-t, acz, apz);
-            region = (t > 0.f && t < 1.f) ? 2 : 4;
+            region = 2; num = d2; den = g22;                       // t along ac
         }
-    } else if (d1 <= 0.f && d2 <= 0.f) {
-        region = 4; p1 = 0.f; p2 = 0.f; dx = apx; dy = apy; dz = apz;
-    } else if (d3 >= 0.f && d4 <= d3) {
-        region = 4; p1 = 1.f; p2 = 0.f; dx = bpx; dy = bpy; dz = bpz;
-    } else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
-        region = 1; t = fdiv(d1, d1 - d3); p1 = t; p2 = 0.f;
-        ex = abx; ey = aby; ez = abz;
-        dx = fmaf(-t, abx, apx); dy = fmaf(-t, aby, apy); dz = fmaf(-t, abz, apz);
-    } else if (d6 >= 0.f && d5 <= d6) {
-        region = 4; p1 = 0.f; p2 = 1.f; dx = cpx; dy = cpy; dz = cpz;
-    } else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
-        region = 2; t = fdiv(d2, d2 - d6); p1 = 0.f; p2 = t;
-        ex = acx; ey = acy; ez = acz;
-        dx = fmaf(-t, acx, apx); dy = fmaf(-t, acy, apy); dz = fmaf(-t, acz, apz);
-    } else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
-        region = 3; t = (d4 - d3) / ((d4 - d3) + (d5 - d6)); p1 = 1.f - t; p2 = t;
-        ex = r2.x - r1.x; ey = r2.y - r1.y; ez = r2.z - r1.z;
-        dx = fmaf(-t, ex, bpx); dy = fmaf(-t, ey, bpy); dz = fmaf(-t, ez, bpz);
+    } else if (d1 <= 0.0 && d2 <= 0.0) {
+        region = 4;
+    } else if (d3 >= 0.0 && d4 <= d3) {
+        region = 4; p1 = 1.0;
     } else {
-        region = 0;
-        float den = frcp(va + vb + vc);
-        p1 = vb * den; p2 = vc * den;
-        // distance to the plane through v0: |(q - v0) . n| / |n|, direction +-n
-        float inv_n = rsqrtf(nn);
-        float h = dot3(apx, apy, apz, nx, ny, nz) * inv_n;
-        dx = h * nx * inv_n; dy = h * ny * inv_n; dz = h * nz * inv_n;
+        const double vc = d1 * d4 - d3 * d2;
+        if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+            region = 1; num = d1; den = d1 - d3;
+        } else if (d6 >= 0.0 && d5 <= d6) {
+            region = 4; p2 = 1.0;
+        } else {
+            const double vb = d5 * d2 - d1 * d6;
+            if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+                region = 2; num = d2; den = d2 - d6;
+            } else {
+                const double va = d3 * d6 - d5 * d4;
+                if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+                    region = 3; num = d4 - d3; den = (d4 - d3) + (d5 - d6);
+                } else {
+                    region = 0; num = vb; num2 = vc; den = va + vb + vc;
+                }
+            }
+        }
     }
-    float d = fsqrt(dot3(dx, dy, dz, dx, dy, dz));
-    Poly2 w = A.tri_uniform ? tri_weight(CoefUniform{A}, p1, p2)
-                            : tri_weight(CoefTable{A.tri_table + 36 * __float_as_int(r0.w)}, p1, p2);
-    float o = region <= 2 ? fabsf(apx) + fabsf(apy) + fabsf(apz)
-                          : (region == 3 ? fabsf(bpx) + fabsf(bpy) + fabsf(bpz) : 0.f);
-    Term r{d, fmaf(S, __logf(w.w), slogA), 0.f, 0.f, 0.f, (d + o) * 0x1p-21f};
+    if (region != 4) {
+        inv_den = den > 0.0 ? 1.0 / den : 0.0;
+        const double t = fmin(fmax(num * inv_den, 0.0), 1.0);   // degenerate edges clamp here
+        if (region == 0) { p1 = num * inv_den; p2 = num2 * inv_den; }
+        else if (region == 1) { p1 = t; }
+        else if (region == 2) { p2 = t; }
+        else { p1 = 1.0 - t; p2 = t; }
+        if (!(nn > 0.0 && det > 0.0) && !(t > 0.0 && t < 1.0)) region = 4;
+    }
+    const double cx = fma(-p2, acx, fma(-p1, abx, apx)), cy = fma(-p2, acy, fma(-p1, aby, apy)),
+                 cz = fma(-p2, acz, fma(-p1, abz, apz));
+    const double s = ddot3(cx, cy, cz, cx, cy, cz);
+    const float r = fsqrt((float)s);
+    const float inv = r > 0.f ? frcp(r) : 0.f;
+    const Poly2 w = A.tri_uniform ? tri_weight(CoefUniform{A}, p1, p2)
+                                  : tri_weight_table(A.tri_table + 36 * __float_as_int(r0.w), p1, p2);
+    const float o1 = (float)(fabs(apx) + fabs(apy) + fabs(apz) + fabs(abx) + fabs(aby) + fabs(abz) +
+                             fabs(acx) + fabs(acy) + fabs(acz));
+    Term o;
+    o.d = sqrt_newton(s, r, inv);
+    o.lw = fmaf(S, __logf((float)w.w), slogA);
+    o.dlo = dist_lo(r, o1);
+    o.gx = o.gy = o.gz = 0.f;
     if (GRAD) {
-        float inv = d > 0.f ? frcp(d) : 0.f;
-        float gx = dx * inv, gy = dy * inv, gz = dz * inv;
-        float k = S * frcp(w.w) * inv_alpha;
+        float gx = (float)cx * inv, gy = (float)cy * inv, gz = (float)cz * inv;
+        float k = S * frcp((float)w.w) * inv_alpha;
         if (metric) k *= inv_alpha;
-        float wgx = 0.f, wgy = 0.f, wgz = 0.f;   // grad w~ (Eq. 5)
+        // grad w~ (Eq. 5) in FP64: the barycentric gradients are large (1 / the
+        // triangle's altitude) and their combination cancels
+        double wgx = 0.0, wgy = 0.0, wgz = 0.0;
         if (region == 0) {
-            // grad phi1 = n x (v0 - v2) / |n|^2, grad phi2 = n x (v1 - v0) / |n|^2
-            float inn = frcp(nn);
-            float g1x = dop(ny, -acz, nz, -acy) * inn, g1y = dop(nz, -acx, nx, -acz) * inn,
-                  g1z = dop(nx, -acy, ny, -acx) * inn;
-            float g2x = dop(ny, abz, nz, aby) * inn, g2y = dop(nz, abx, nx, abz) * inn,
-                  g2z = dop(nx, aby, ny, abx) * inn;
-            wgx = fmaf(w.wx, g1x, w.wy * g2x);
-            wgy = fmaf(w.wx, g1y, w.wy * g2y);
-            wgz = fmaf(w.wx, g1z, w.wy * g2z);
+            // grad phi1 = (g22 ab - g12 ac) / det, grad phi2 = (g11 ac - g12 ab) / det
+            // (va + vb + vc = det is the face region's denominator)
+            const double c1 = (w.wx * g22 - w.wy * g12) * inv_den, c2 = (w.wy * g11 - w.wx * g12) * inv_den;
+            wgx = fma(c1, abx, c2 * acx);
+            wgy = fma(c1, aby, c2 * acy);
+            wgz = fma(c1, abz, c2 * acz);
         } else if (region != 4) {
-            float ee = dot3(ex, ey, ez, ex, ey, ez);
-            float dwdt = region == 1 ? w.wx : (region == 2 ? w.wy : w.wy - w.wx);
-            float c = fdiv(dwdt, ee);
+            // along the edge e: d t / dq = e / |e|^2 for the edge's parameter t
+            // (the edge regions' denominator den is |e|^2)
+            double ex, ey, ez, dwdt;
+            if (region == 1) { ex = abx; ey = aby; ez = abz; dwdt = w.wx; }
+            else if (region == 2) { ex = acx; ey = acy; ez = acz; dwdt = w.wy; }
+            else { ex = acx - abx; ey = acy - aby; ez = acz - abz; dwdt = w.wy - w.wx; }
+            const double c = dwdt * inv_den;
             wgx = c * ex; wgy = c * ey; wgz = c * ez;
         }
-        r.gx = fmaf(-k, wgx, gx);
-        r.gy = fmaf(-k, wgy, gy);
-        r.gz = fmaf(-k, wgz, gz);
+        o.gx = fmaf(-k, (float)wgx, gx);
+        o.gy = fmaf(-k, (float)wgy, gy);
+        o.gz = fmaf(-k, (float)wgz, gz);
     }
-    return r;
+    return o;
 }
 
 // ---------------------------------------------------------------------------
@@ -328,14 +382,17 @@ __device__ __forceinline__ Term leaf_term(const TreeView &T, const EvalArgs &A, 
                                           float qx, float qy, float qz, bool metric) {
     if (CLS == 0) return point_term<GRAD>(lo, qx, qy, qz);
     if (CLS == 1)
-        return edge_term<GRAD>(T.leaf[2 * slot], T.leaf[2 * slot + 1], qx, qy, qz, A.S, T.slogA,
+        return edge_term<GRAD>(T.leaf[2 * slot], T.leaf[2 * slot + 1], qx, qy, qz, A.S, (float)T.slogA,
                                A.inv_alpha, metric);
     return tri_term<GRAD>(T.leaf[3 * slot], T.leaf[3 * slot + 1], T.leaf[3 * slot + 2], qx, qy, qz, A,
-                          T.slogA, metric);
+                          (float)T.slogA, metric);
 }
 
-// One node of Alg. 1: the opening test, then the far-field term (App. D) or a
-// leaf hand-off or descent.  Returns the leaf slot to evaluate, or -1.
+// log-term of a leaf term: L = log w - alpha d
+__device__ __forceinline__ double log_term(const EvalArgs &A, const Term &t) {
+    return fma(-A.alpha64, t.d, (double)t.lw);
+}
+
 // a node record is 32 B (lo, hi); a 32-bit byte offset from the array base
 // gives the loads' scalar-base + vector-offset form (node counts stay far
 // below 2^27, which the build checks)
@@ -355,29 +412,29 @@ template <bool GRAD, bool COUNT, bool PRUNE>
 __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, float qx, float qy,
                                           float qz, LSE &st, float4 &lo, float4 &hi, int &node,
                                           float4 &leaf_lo, int &n_vis, int &n_far) {
-    float yx = clampf(qx, lo.x, hi.x);
-    float yy = clampf(qy, lo.y, hi.y);
-    float yz = clampf(qz, lo.z, hi.z);
-    float dx = qx - yx, dy = qy - yy, dz = qz - yz;
-    float D2 = dot3(dx, dy, dz, dx, dy, dz);
-    float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
-    float diag2 = dot3(ex, ey, ez, ex, ey, ez);
-    int esc = __float_as_int(lo.w);
-    int pay = __float_as_int(hi.w);
+    const float yx = clampf(qx, lo.x, hi.x);
+    const float yy = clampf(qy, lo.y, hi.y);
+    const float yz = clampf(qz, lo.z, hi.z);
+    const float dx = qx - yx, dy = qy - yy, dz = qz - yz;
+    const float D2 = dot3(dx, dy, dz, dx, dy, dz);
+    const float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
+    const float diag2 = dot3(ex, ey, ez, ex, ey, ez);
+    const int esc = __float_as_int(lo.w);
+    const int pay = __float_as_int(hi.w);
     if (COUNT) ++n_vis;
-    float logn = pay < 0 ? 0.f : hi.w;
+    const float logn = pay < 0 ? 0.f : hi.w;
     // Negligible subtree: every term below this node is at most
     // n_B W_max exp(-alpha D) (D <= each d_i), i.e. its exponent relative to
-    // the running reference is below -A.prune (64: < 1e-27 of the sum), so it
-    // cannot change the FP32 result; skip it.  D > d* + (log n_B + log W_max
-    // - l* + prune)/alpha, tested on squares.
+    // the running maximum is below -A.prune (64: < 1e-27 of the sum), so it
+    // cannot change the FP32 result; skip it.
+    // D > (log n_B + log W_max - L* + prune) / alpha, tested on squares.
     bool skip = false;
     if (PRUNE) {
-        float thr = fmaf(logn + T.lwmax - st.lref + A.prune, A.inv_alpha, st.dref);
+        const float thr = (logn + T.lwmax - st.Lf + A.prune) * A.inv_alpha;
         skip = thr < 0.f || D2 > thr * thr;
     }
-    bool far = !skip && diag2 < A.beta2 * D2;
-    bool leaf = !skip && !far && pay < 0;
+    const bool far = !skip && diag2 < A.beta2 * D2;
+    const bool leaf = !skip && !far && pay < 0;
     int slot = -1;
     if (leaf) {
         slot = pay & 0x7fffffff;
@@ -388,14 +445,13 @@ __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, 
     if (far) {
         // far field at the closest box point y_B: weight n_B A^S (App. D).
         // D > 0 here: the test passed, so D^2 > |B|^2 / beta^2 >= 0.  The
-        // distance enters rounded down by D 2^-21 (one rounding of
-        // D (1 - 2^-21), a representable factor).  (D = D^2 rsq(D^2) would
-        // save a transcendental, but its 2-3 ulp error shows in gradients at
-        // large alpha.)
-        float D = fsqrt(D2);
-        float inv = frcp(D);
-        float lw = logn + T.slogA;
-        lse_add<GRAD>(st, D * A.far_scale, lw, dx * inv, dy * inv, dz * inv, A.alpha);
+        // distance in FP64 from the exact differences q - y_B.
+        const float D = fsqrt(D2);
+        const float inv = frcp(D);
+        const double ux = (double)qx - (double)yx, uy = (double)qy - (double)yy, uz = (double)qz - (double)yz;
+        const double D64 = sqrt_newton(ddot3(ux, uy, uz, ux, uy, uz), D, inv);
+        const double L = fma(-A.alpha64, D64, (double)logn + T.slogA);
+        lse_add<GRAD>(st, L, D * kLo, dx * inv, dy * inv, dz * inv);
         if (COUNT) ++n_far;
     }
     return slot;
@@ -404,16 +460,16 @@ __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, 
 // Alg. 1 over one class hierarchy, stackless (escape indices).  Exact leaf
 // terms are expensive and rare (a few percent of the nodes a query visits),
 // so a lane that reaches a leaf queues it and the wave evaluates queued leaves
-// together once at least defer/64 of its live lanes hold one (or none can
-// continue); far-field terms are added inline.  The set of terms, and so the
-// value up to summation order, is that of the recursive Alg. 1.
+// together once some lane's queue is full (or none can continue); far-field
+// terms are added inline.  The set of terms, and so the value up to summation
+// order, is that of the recursive Alg. 1.
 // Reference for the running maximum before any term is seen: descend to the
 // leaf whose box is nearest at every level and take the lower bound
 // -alpha (D_leaf + |leaf box| + 1/alpha) of that leaf's term (its weight is
 // >= 1 up to rounding).  The traversal's largest term is at least this large
 // (the leaf, or a far-field ancestor of it, enters the sum), so s cannot
 // underflow, and most terms then fall below the reference, which keeps the
-// rescaling branch of lse_add rare across a wave.
+// rescaling branch of lse_fold rare across a wave.
 __device__ __forceinline__ float seed_distance(const TreeView &T, float qx, float qy, float qz,
                                                float inv_alpha) {
     int node = 0;
@@ -438,8 +494,24 @@ __device__ __forceinline__ float seed_distance(const TreeView &T, float qx, floa
     return fsqrt(dot3(dx, dy, dz, dx, dy, dz)) + fsqrt(dot3(ex, ey, ez, ex, ey, ez)) + inv_alpha;
 }
 
+__device__ __forceinline__ void lse_seed(LSE &st, const TreeView &T, const EvalArgs &A, float qx, float qy,
+                                         float qz) {
+    if (st.s == 0.0 && st.L == -INFINITY) {
+        const float sd = seed_distance(T, qx, qy, qz, A.inv_alpha);
+        if (sd == sd) {   // NaN queries keep the empty reference
+            st.L = -A.alpha64 * (double)sd;
+            st.Lf = (float)st.L;
+        }
+    }
+}
+
 // Per-wave LDS queue of the cooperative leaf stage: queued leaf slots and their
-// results, lane-minor so that the 64 lanes touch consecutive banks.
+// results, lane-minor so that the 64 lanes touch consecutive banks.  A result
+// is the term's exponent relative to the owner's reference at the time of the
+// flush as an unevaluated sum of two floats (so that a term that becomes the
+// new reference enters with its exact log-term) and its gradient direction;
+// the worker that evaluated entry (k, owner) overwrites the slot it read with
+// the term's distance lower bound.
 #ifndef SD_LEAF_QUEUE
 #define SD_LEAF_QUEUE 5
 #endif
@@ -458,6 +530,21 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Fold the owner's queued results: entry k has exponent t_k relative to the
+// reference `base` the owner held at the flush (rescalings by earlier entries
+// move the reference, so each exponent is re-based in FP64).
+template <bool GRAD>
+__device__ __forceinline__ void fold_queue(LSE &st, const LeafQueue &lq, int cnt, int lane) {
+    const double base = st.L;
+    for (int k = 0; k < cnt; ++k) {
+        float gx = 0.f, gy = 0.f, gz = 0.f;
+        if (GRAD) { gx = lq.res[k][2][lane]; gy = lq.res[k][3][lane]; gz = lq.res[k][4][lane]; }
+        const double Lk = (base + (double)lq.res[k][0][lane]) + (double)lq.res[k][1][lane];
+        st.mlo = fminf(st.mlo, __int_as_float(lq.slot[k][lane]));
+        lse_fold<GRAD>(st, (float)(Lk - st.L), Lk, gx, gy, gz);
+    }
+}
+
 template <int CLS, bool GRAD, bool COUNT, bool PRUNE>
 __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, float qx, float qy,
                                          float qz, LSE &st, int &n_vis, int &n_far, int &n_leaf,
@@ -465,13 +552,7 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
     const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
     int node = (active && T.n_nodes > 0) ? 0 : -1;
     float4 leaf_lo = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (node >= 0 && st.s == 0.0 && st.dref == INFINITY) {
-        float sd = seed_distance(T, qx, qy, qz, A.inv_alpha);
-        if (sd == sd) {   // NaN queries keep the empty reference
-            st.dref = sd;
-            st.lref = 0.f;
-        }
-    }
+    if (node >= 0) lse_seed(st, T, A, qx, qy, qz);
     // (lo, hi): the record of `node` while node >= 0, loaded one step ahead
     float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
     if (node >= 0) load_node(T, node, lo, hi);
@@ -485,7 +566,7 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
                     if (slot >= 0) {
                         if (COUNT) ++n_leaf;
                         Term t = leaf_term<CLS, GRAD>(T, A, slot, leaf_lo, qx, qy, qz, metric);
-                        lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
+                        lse_add<GRAD>(st, log_term(A, t), t.dlo, t.gx, t.gy, t.gz);
                     }
                 }
             } while (__builtin_amdgcn_sicmp(node, 0, 39) != 0);
@@ -495,8 +576,9 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
     // Wave-cooperative leaves: a lane that reaches a leaf queues its slot (up to
     // kQ per lane) in the wave's LDS queue and keeps traversing.  When a lane's
     // queue is full, or no lane can continue, the wave evaluates every queued
-    // (query, leaf) pair with all lanes busy (the owner's query is read with a
-    // lane shuffle), then each owner folds its results into its own sum.
+    // (query, leaf) pair with all lanes busy (the owner's query and reference
+    // are read with lane shuffles), then each owner folds its results into its
+    // own sum.
     const int lane = __lane_id();
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     int cnt = 0;
@@ -541,16 +623,21 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
         // past the end of the query array have already exited)
         const uint64_t present = __ballot(true);
         const int rank = __popcll(present & lt), npresent = __popcll(present);
+        const int Lhi = __double2hiint(st.L), Llo = __double2loint(st.L);
         for (int base = 0; base < total; base += npresent) {
             int e = base + rank;
             bool act = e < total;
             int code = act ? lq.ent[e] : 0;
             int owner = code >> 3, k = code & 7;
             float ox = __shfl(qx, owner, 64), oy = __shfl(qy, owner, 64), oz = __shfl(qz, owner, 64);
+            const double oL = __hiloint2double(__shfl(Lhi, owner, 64), __shfl(Llo, owner, 64));
             if (act) {
                 Term t = leaf_term<CLS, GRAD>(T, A, lq.slot[k][owner], leaf_lo, ox, oy, oz, metric);
-                lq.res[k][0][owner] = fmaf(-A.cons, t.err, t.d);
-                lq.res[k][1][owner] = t.lw;
+                const double tk = log_term(A, t) - oL;
+                const float thi = (float)tk;
+                lq.res[k][0][owner] = thi;
+                lq.res[k][1][owner] = (float)(tk - (double)thi);
+                lq.slot[k][owner] = __float_as_int(t.dlo);
                 if (GRAD) {
                     lq.res[k][2][owner] = t.gx;
                     lq.res[k][3][owner] = t.gy;
@@ -559,11 +646,7 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
             }
         }
         wave_sync();
-        for (int k = 0; k < cnt; ++k) {
-            float gx = 0.f, gy = 0.f, gz = 0.f;
-            if (GRAD) { gx = lq.res[k][2][lane]; gy = lq.res[k][3][lane]; gz = lq.res[k][4][lane]; }
-            lse_add<GRAD>(st, lq.res[k][0][lane], lq.res[k][1][lane], gx, gy, gz, A.alpha);
-        }
+        fold_queue<GRAD>(st, lq, cnt, lane);
         cnt = 0;
         wave_sync();
     }
@@ -822,7 +905,7 @@ __device__ __forceinline__ V3 closest_on_query(const V3 (&dv)[3], const V3 (&gv)
 // before anything is formed, so that g(lambda) carries rounding of the size
 // of the local offsets rather than of the absolute coordinates (the terms are
 // translation invariant; the weight data in .w is kept); the rounding of
-// g(lambda) adds 2^-20 |g(lambda)|_1 to the error bound.
+// g(lambda) lowers the distance bound by 2^-20 |g(lambda)|_1.
 template <int CLS, bool GRAD, int NV>
 __device__ __forceinline__ Term leaf_term_q(const TreeView &T, const EvalArgs &A, int slot, float4 leaf_lo,
                                             const QPrim<NV> &g, bool metric) {
@@ -851,12 +934,12 @@ __device__ __forceinline__ Term leaf_term_q(const TreeView &T, const EvalArgs &A
         t = point_term<GRAD>(make_float4(0.f, 0.f, 0.f, r[0].w), q.x, q.y, q.z);
     } else if (CLS == 1) {
         t = edge_term<GRAD>(make_float4(0.f, 0.f, 0.f, r[0].w), make_float4(dv[1].x, dv[1].y, dv[1].z, r[1].w),
-                            q.x, q.y, q.z, A.S, T.slogA, A.inv_alpha, metric);
+                            q.x, q.y, q.z, A.S, (float)T.slogA, A.inv_alpha, metric);
     } else {
         t = tri_term<GRAD>(make_float4(0.f, 0.f, 0.f, r[0].w), make_float4(dv[1].x, dv[1].y, dv[1].z, r[1].w),
-                           make_float4(dv[2].x, dv[2].y, dv[2].z, r[2].w), q.x, q.y, q.z, A, T.slogA, metric);
+                           make_float4(dv[2].x, dv[2].y, dv[2].z, r[2].w), q.x, q.y, q.z, A, (float)T.slogA, metric);
     }
-    t.err = fmaf(0x1p-20f, fabsf(q.x) + fabsf(q.y) + fabsf(q.z), t.err);
+    t.dlo = fmaf(-0x1p-20f, fabsf(q.x) + fabsf(q.y) + fabsf(q.z), t.dlo);
     return t;
 }
 
@@ -884,9 +967,12 @@ __device__ __forceinline__ int node_visit_q(const TreeView &T, const EvalArgs &A
     node = (far || leaf) ? esc : node + 1;
     if (node >= 0) load_node(T, node, lo, hi);
     if (far) {
+        // the gaps are rounded FP32 differences: the FP32 distance is as
+        // accurate as the far-field box distance can be here
         float D = fsqrt(D2);
         float inv = frcp(D);
-        lse_add<GRAD>(st, D * A.far_scale, logn + T.slogA, dx * inv, dy * inv, dz * inv, A.alpha);
+        const double L = fma(-A.alpha64, (double)D, (double)logn + T.slogA);
+        lse_add<GRAD>(st, L, D * kLo, dx * inv, dy * inv, dz * inv);
     }
     return slot;
 }
@@ -900,14 +986,8 @@ __device__ __forceinline__ void traverse_q(const TreeView &T, const EvalArgs &A,
     const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
     int node = T.n_nodes > 0 ? 0 : -1;
     float4 leaf_lo = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (node >= 0 && st.s == 0.0 && st.dref == INFINITY) {
-        // any vertex of g bounds the distance to the seed leaf from above
-        float sd = seed_distance(T, g.v[0].x, g.v[0].y, g.v[0].z, A.inv_alpha);
-        if (sd == sd) {
-            st.dref = sd;
-            st.lref = 0.f;
-        }
-    }
+    // any vertex of g bounds the distance to the seed leaf from above
+    if (node >= 0) lse_seed(st, T, A, g.v[0].x, g.v[0].y, g.v[0].z);
     float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
     if (node >= 0) load_node(T, node, lo, hi);
     if (CLS == 0 || A.defer == 0) {
@@ -917,7 +997,7 @@ __device__ __forceinline__ void traverse_q(const TreeView &T, const EvalArgs &A,
                     int slot = node_visit_q<GRAD, NV>(T, A, g, st, lo, hi, node, leaf_lo);
                     if (slot >= 0) {
                         Term t = leaf_term_q<CLS, GRAD, NV>(T, A, slot, leaf_lo, g, metric);
-                        lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
+                        lse_add<GRAD>(st, log_term(A, t), t.dlo, t.gx, t.gy, t.gz);
                     }
                 }
             } while (__builtin_amdgcn_sicmp(node, 0, 39) != 0);
@@ -957,19 +1037,24 @@ __device__ __forceinline__ void traverse_q(const TreeView &T, const EvalArgs &A,
         wave_sync();
         const uint64_t present = __ballot(true);
         const int rank = __popcll(present & lt), npresent = __popcll(present);
+        const int Lhi = __double2hiint(st.L), Llo = __double2loint(st.L);
         for (int base = 0; base < total; base += npresent) {
             int e = base + rank;
             bool act = e < total;
             int code = act ? lq.ent[e] : 0;
             int owner = code >> 3, k = code & 7;
+            const double oL = __hiloint2double(__shfl(Lhi, owner, 64), __shfl(Llo, owner, 64));
             QPrim<NV> og;
 #pragma unroll
             for (int v = 0; v < NV; ++v)
                 og.v[v] = v3m(__shfl(g.v[v].x, owner, 64), __shfl(g.v[v].y, owner, 64), __shfl(g.v[v].z, owner, 64));
             if (act) {
                 Term t = leaf_term_q<CLS, GRAD, NV>(T, A, lq.slot[k][owner], leaf_lo, og, metric);
-                lq.res[k][0][owner] = fmaf(-A.cons, t.err, t.d);
-                lq.res[k][1][owner] = t.lw;
+                const double tk = log_term(A, t) - oL;
+                const float thi = (float)tk;
+                lq.res[k][0][owner] = thi;
+                lq.res[k][1][owner] = (float)(tk - (double)thi);
+                lq.slot[k][owner] = __float_as_int(t.dlo);
                 if (GRAD) {
                     lq.res[k][2][owner] = t.gx;
                     lq.res[k][3][owner] = t.gy;
@@ -978,11 +1063,7 @@ __device__ __forceinline__ void traverse_q(const TreeView &T, const EvalArgs &A,
             }
         }
         wave_sync();
-        for (int k = 0; k < cnt; ++k) {
-            float gx = 0.f, gy = 0.f, gz = 0.f;
-            if (GRAD) { gx = lq.res[k][2][lane]; gy = lq.res[k][3][lane]; gz = lq.res[k][4][lane]; }
-            lse_add<GRAD>(st, lq.res[k][0][lane], lq.res[k][1][lane], gx, gy, gz, A.alpha);
-        }
+        fold_queue<GRAD>(st, lq, cnt, lane);
         cnt = 0;
         wave_sync();
     }
@@ -998,35 +1079,24 @@ __device__ __forceinline__ int xcd_block(int i, int G) {
     return x * q + min(x, r) + k;
 }
 
+// Alg. 2: d = -(L* + log s) / alpha in FP64, rounded once to FP32; grad = G / s.
+// By default d is then clamped to the smallest lower bound of a term distance
+// (see the head of this file), which keeps d <= d_min in FP32.
 template <bool GRAD>
 __device__ __forceinline__ void final_value(const EvalArgs &A, const LSE &st, float &d, float &gx,
                                             float &gy, float &gz) {
-    float sum = (float)st.s;
     gx = gy = gz = 0.f;
-    if (!(sum > 0.f) && !(sum != sum)) {
+    if (!(st.s > 0.0) && !(st.s != st.s)) {
         d = INFINITY;   // empty scene: the empty sum
-    } else {
-        // |lref| + |log sum| bounds the magnitudes the correction is formed from
-        float mag;
-        if (A.flags & SD_ROOTLOG_F64) {
-            double s64 = st.s;
-            double ls = log(s64);
-            double dd = (double)st.dref - ((double)st.lref + ls) * (double)A.inv_alpha;
-            mag = (float)((fabs((double)st.lref) + fabs(ls)) * (double)A.inv_alpha);
-            d = (float)dd;
-        } else {
-            float ls = logf(sum);
-            d = st.dref - (st.lref + ls) * A.inv_alpha;
-            mag = (fabsf(st.lref) + fabsf(ls)) * A.inv_alpha;
-        }
-        if (!(A.flags & SD_NO_CONSERVATIVE_ROUNDING))
-            d -= A.margin_scale * (fabsf(st.dref) + mag);
-        if (GRAD) {
-            float inv = 1.f / sum;
-            gx = (float)st.gx * inv;
-            gy = (float)st.gy * inv;
-            gz = (float)st.gz * inv;
-        }
+        return;
+    }
+    d = (float)(-(st.L + log(st.s)) * A.inv_alpha64);
+    if (A.clamp && d > st.mlo) d = st.mlo;   // NaN stays NaN
+    if (GRAD) {
+        const double inv = 1.0 / st.s;
+        gx = (float)(st.gx * inv);
+        gy = (float)(st.gy * inv);
+        gz = (float)(st.gz * inv);
     }
 }
 
@@ -1042,10 +1112,6 @@ __device__ __forceinline__ void finalize(const EvalArgs &A, const LSE &st, int q
     }
 }
 
-__device__ __forceinline__ void lse_init(LSE &st) {
-    st.dref = INFINITY; st.lref = 0.f;
-    st.s = st.gx = st.gy = st.gz = 0.0;
-}
 
 // Waves per SIMD the traversal is compiled for (register budget): four, i.e.
 // at most 128 registers.  Single-class variants fit without it (triangles:
@@ -1096,12 +1162,12 @@ __device__ __forceinline__ void brute_class(const TreeView &T, int64_t n, const 
             Term t;
             if (CLS == 0) t = point_term<GRAD>(tile[j], qx, qy, qz);
             else if (CLS == 1)
-                t = edge_term<GRAD>(tile[2 * j], tile[2 * j + 1], qx, qy, qz, A.S, T.slogA,
+                t = edge_term<GRAD>(tile[2 * j], tile[2 * j + 1], qx, qy, qz, A.S, (float)T.slogA,
                                     A.inv_alpha, metric);
             else
                 t = tri_term<GRAD>(tile[3 * j], tile[3 * j + 1], tile[3 * j + 2], qx, qy, qz,
-                                   A, T.slogA, metric);
-            lse_add<GRAD>(st, fmaf(-A.cons, t.err, t.d), t.lw, t.gx, t.gy, t.gz, A.alpha);
+                                   A, (float)T.slogA, metric);
+            lse_add<GRAD>(st, log_term(A, t), t.dlo, t.gx, t.gy, t.gz);
         }
     }
 }
@@ -1335,10 +1401,7 @@ static int make_args(const sd_scene *sc, const sd_params *p, EvalArgs &A) {
         A.tree[c].hi = sc->hi[c];
         A.tree[c].leaf = sc->leaf[c];
         A.tree[c].n_nodes = (int32_t)sc->n_nodes[c];
-        double sl = S * log(sc->A[c]);
-        float f = (float)sl;
-        if ((double)f < sl) f = nextafterf(f, INFINITY);   // far-field weights round up
-        A.tree[c].slogA = f;
+        A.tree[c].slogA = S * log(sc->A[c]);
         // largest possible log-weight of any term of the class (pruning bound):
         // w~ <= 1 + |a - b|/2 <= 1.5 for edges, <= the largest Bernstein
         // coefficient for triangles (convex hull), w = 1 for points
@@ -1346,15 +1409,15 @@ static int make_args(const sd_scene *sc, const sd_params *p, EvalArgs &A) {
         A.tree[c].lwmax = (float)(S * (log(sc->A[c]) + log(wmax))) + 1e-3f;
     }
     A.tri_uniform = sc->n_tri_classes <= 1 ? 1 : 0;
-    memcpy(A.tri_coef, sc->tri_coef0, sizeof(A.tri_coef));
+    memcpy(A.tri_mono, sc->tri_mono0, sizeof(A.tri_mono));
     A.tri_table = sc->tri_table;
     A.alpha = p->alpha;
     A.inv_alpha = (float)(1.0 / alpha);
     A.beta2 = p->beta * p->beta;
     A.S = (float)S;
-    A.margin_scale = ldexpf(1.f, -22);
-    A.cons = (p->flags & SD_NO_CONSERVATIVE_ROUNDING) ? 0.f : 1.f;
-    A.far_scale = (p->flags & SD_NO_CONSERVATIVE_ROUNDING) ? 1.f : 1.f - 0x1p-21f;
+    A.alpha64 = alpha;
+    A.inv_alpha64 = 1.0 / alpha;
+    A.clamp = (p->flags & SD_NO_CONSERVATIVE_ROUNDING) ? 0 : 1;
     A.defer = defer_threshold();
     A.prune = 64.f;
     A.flags = p->flags;

@@ -68,7 +68,7 @@ class AsyncScratch {
 //
 //   node_lo[i] = (min.x, min.y, min.z, bits: escape index, -1 = end)
 //   node_hi[i] = (max.x, max.y, max.z, payload)
-//   payload: internal node -> float log(n_B) rounded up (n_B = leaves below);
+//   payload: internal node -> float log(n_B), round to nearest (n_B = leaves below);
 //            leaf           -> int bits 0x80000000 | leaf slot.
 //   The left child of internal node i is i + 1; its right child is the left
 //   child's escape index.
@@ -84,21 +84,21 @@ struct TreeView {
     const float4 *hi;
     const float4 *leaf;   // edges / triangles only
     int32_t n_nodes;
-    float slogA;          // S log A of the class, filled per evaluation
     float lwmax;          // bound on the log-weight of any term of the class
+    double slogA;         // S log A of the class, filled per evaluation
 };
 
 struct EvalArgs {
     TreeView tree[3];
-    // Triangle weights (App. C.3) as degree-7 Bernstein coefficients per
-    // valence class, 36 per class; a single class is passed by value.
-    float tri_coef[36];
-    const float *tri_table;   // n_classes x 36 (class id in the leaf record)
-    int32_t tri_uniform;      // 1: every triangle uses tri_coef
+    // Triangle weights (App. C.3) as the 36 FP64 monomial coefficients of
+    // each valence class in Horner order (see triangle_monomial_horner); a
+    // single class is passed by value.
+    double tri_mono[36];
+    const double *tri_table;  // n_classes x 36 (class id in the leaf record)
+    int32_t tri_uniform;      // 1: every triangle uses tri_mono
     float alpha, inv_alpha, beta2, S;
-    float margin_scale;   // final rounding margin: 2^-22 (|d*| + |log-sum term|)
-    float cons;           // 1: each term enters at its rounded-down distance (default)
-    float far_scale;      // far-field distance factor: 1 - 2^-21 with cons, else 1
+    double alpha64, inv_alpha64;
+    int32_t clamp;        // 1: result clamped to a lower bound of the smallest term distance (default)
     int32_t defer;        // 1: wave-cooperative leaf stage, 0: leaves evaluated inline
     float prune;          // skip subtrees whose terms are below exp(-prune) of the reference
     uint32_t flags;
@@ -115,6 +115,9 @@ struct EvalArgs {
 int triangle_basis_f64(double out[3][64]);
 double triangle_weight_min_f64(int v, int e);   // min over the barycentric triangle
 void triangle_bernstein(int v, int e, float out[36]);
+// monomial coefficients c_ab of w~ for (v, e) in Horner order: a = 7 .. 0,
+// and for each a, b = 7 - a .. 0 (w~ = 1 for v <= 1)
+void triangle_monomial_horner(int v, int e, double out[36]);
 
 // Sorting and scans (sort.hip)
 size_t radix_sort_temp_bytes(int64_t n);
@@ -140,8 +143,8 @@ struct sd_scene {
     double diam_max = 0.0;
     float box[6] = {0, 0, 0, 0, 0, 0};                    // union of class boxes
     int32_t n_tri_classes = 0;
-    float *tri_table = nullptr;                           // n_tri_classes x 36 Bernstein coefs
-    float tri_coef0[36];                                  // host copy of class 0
+    double *tri_table = nullptr;                          // n_tri_classes x 36 monomial coefs (Horner order)
+    double tri_mono0[36];                                 // host copy of class 0
     double tri_wmax = 1.0;                                // largest Bernstein coefficient
     int64_t device_bytes = 0;
     int device = 0;

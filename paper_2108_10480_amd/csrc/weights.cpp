@@ -209,6 +209,21 @@ void triangle_bernstein(int v, int e, float out[36]) {
         }
 }
 
+// Monomial coefficients c_ab of w~ for valences (v, e) in the order the
+// device evaluates them (Horner in phi1 outside, in phi2 inside): a = 7 down to
+// 0, and for each a, b = 7 - a down to 0.  FP64 throughout; w~ = 1 for v <= 1.
+void triangle_monomial_horner(int v, int e, double out[36]) {
+    ensure_basis();
+    int t = 0;
+    for (int a = 7; a >= 0; --a)
+        for (int b = 7 - a; b >= 0; --b) {
+            const int k = a * 8 + b;
+            out[t++] = v <= 1 ? (k == 0 ? 1.0 : 0.0)
+                              : (1.0 / v) * g_basis[0][k] + (1.0 / e) * g_basis[1][k] +
+                                    ((v - 1.0) / v) * g_basis[2][k];
+        }
+}
+
 // Minimum of w~ over {phi1, phi2 >= 0, phi1 + phi2 <= 1}: grid, then a compass
 // search kept inside the simplex from the best grid points.
 double triangle_weight_min_f64(int v, int e) {

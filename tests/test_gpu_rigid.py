@@ -83,8 +83,7 @@ def test_autograd_function_matches_oracle_finite_differences():
     Xt = cuda(X).requires_grad_(True)
     Rt = cuda(R).requires_grad_(True)
     tt = cuda(t).requires_grad_(True)
-    d = api.rigid_smooth_distance(Xt, Rt, tt, scene, alpha, beta=0.0,
-                                  flags=api.SD_NO_CONSERVATIVE_ROUNDING)
+    d = api.rigid_smooth_distance(Xt, Rt, tt, scene, alpha, beta=0.0)
     (d * cuda(gbar.astype(np.float32))).sum().backward()
 
     def loss(Xd, Rd, td):
@@ -124,7 +123,7 @@ def test_street_scene_rigid_step_matches_oracle():
     scene = api.upload_scene(sc)
     R, t = scenes.rigid_transforms(6, seed=5)
     Q = api.sd_rigid_transform(cuda(body), cuda(R), cuda(t))
-    d, g = api.sd_eval_grad(scene, Q, 50.0, 0.5, flags=api.SD_NO_CONSERVATIVE_ROUNDING)
+    d, g = api.sd_eval_grad(scene, Q, 50.0, 0.5)
     Qn = Q.cpu().numpy().astype(np.float64)
     osc = oracle_scene(sc)
     dr, gr, st = O.barnes_hut(osc, oracle_trees(scene), Qn, 50.0, 0.5, cut_f32=True)
