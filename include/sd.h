@@ -136,6 +136,23 @@ int sd_eval_grad(const sd_scene *scene, const float *Q, int64_t nQ, const sd_par
                  float *d_out, float *grad_out, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sd_eval_grad
+ * with the same arguments and the same results, bit for bit, that allocates
+ * nothing.  The query ordering's scratch (Morton keys and radix-sort buffers,
+ * about 24 bytes per query) lives in a static device array inside the library:
+ * every GPU the library runs on holds one copy (28 MiB) from the first call on
+ * that GPU until the process ends.  Limit: nQ <= SD_NOALLOC_MAX_QUERIES per
+ * call (SD_EINVAL above it; split larger batches).  All calls on one GPU share
+ * that GPU's array: calls that overlap in time on one GPU (different streams
+ * or host threads without ordering between them) race and must not be made.
+ * Inputs, outputs and errors as sd_eval_grad.
+ */
+#define SD_NOALLOC_MAX_QUERIES (1 << 20)
+int sd_eval_grad_noalloc(const sd_scene *scene, const float *Q, int64_t nQ, const sd_params *params,
+                         float *d_out, float *grad_out, void *stream);
+
+/*
  * Query ordering for coherent traversal: perm_out (nQ uint32) receives the
  * query indices sorted by 30-bit Morton code in the scene box enlarged by half
  * its extent on each side (a stable radix sort; ties keep input order).

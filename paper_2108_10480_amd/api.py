@@ -50,7 +50,7 @@ _lib = None
 
 EXPORTED = ["sd_build_bvh", "sd_free_scene", "sd_scene_info_get", "sd_eval", "sd_eval_grad",
             "sd_eval_brute", "sd_eval_counters", "sd_export_bvh", "sd_export_weights",
-            "sd_query_order", "sd_eval_grad_ordered",
+            "sd_query_order", "sd_eval_grad_ordered", "sd_eval_grad_noalloc",
             "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint", "sd_query_mesh_lse", "sd_sphere_trace", "sd_eval_grad_prims",
             "sd_surrogate_create", "sd_surrogate_free", "sd_surrogate_forward",
             "sd_surrogate_loss_grad", "sd_surrogate_adam", "sd_surrogate_train_step",
@@ -169,6 +169,22 @@ def sd_eval_grad(scene, Q, alpha, beta=0.5, alpha_u=0.0, flags=0, out=None, grad
     p = params(alpha, beta, alpha_u, flags)
     _check(lib().sd_eval_grad(scene.handle, Qp, _i64(n), ctypes.byref(p), _c_p(d.data_ptr()),
                               _c_p(g.data_ptr()), _stream()))
+    return d, g
+
+
+SD_NOALLOC_MAX_QUERIES = 1 << 20
+
+
+def sd_eval_grad_noalloc(scene, Q, alpha, beta=0.5, alpha_u=0.0, flags=0, out=None, grad_out=None):
+    """sd_eval_grad through the entry point that allocates no device memory
+    (at most SD_NOALLOC_MAX_QUERIES queries per call).  Pass `out` and
+    `grad_out` to keep the call itself free of allocations."""
+    Qp, n = _queries(Q)
+    d = out if out is not None else torch.empty(n, dtype=torch.float32, device=Q.device)
+    g = grad_out if grad_out is not None else torch.empty((n, 3), dtype=torch.float32, device=Q.device)
+    p = params(alpha, beta, alpha_u, flags)
+    _check(lib().sd_eval_grad_noalloc(scene.handle, Qp, _i64(n), ctypes.byref(p), _c_p(d.data_ptr()),
+                                      _c_p(g.data_ptr()), _stream()))
     return d, g
 
 

@@ -145,6 +145,13 @@ int sd_eval_grad(const sd_scene *sc, const float *Q, int64_t nQ, const sd_params
     return sd::eval_dispatch(sc, Q, nullptr, nQ, p, d_out, grad_out, nullptr, false, (hipStream_t)stream);
 }
 
+int sd_eval_grad_noalloc(const sd_scene *sc, const float *Q, int64_t nQ, const sd_params *p, float *d_out,
+                         float *grad_out, void *stream) {
+    SD_TRY(sd::check_eval(sc, Q, nQ, p, d_out, "sd_eval_grad_noalloc"));
+    if (nQ > 0 && !grad_out) return sd::fail(SD_EINVAL, "sd_eval_grad_noalloc: null grad_out");
+    return sd::eval_grad_noalloc(sc, Q, nQ, p, d_out, grad_out, (hipStream_t)stream);
+}
+
 int sd_query_order(const sd_scene *sc, const float *Q, int64_t nQ, uint32_t *perm_out,
                    void *stream) {
     if (!sc) return sd::fail(SD_EINVAL, "sd_query_order: null scene");

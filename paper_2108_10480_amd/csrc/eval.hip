@@ -35,6 +35,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "sd_internal.h"
 
@@ -1351,21 +1352,32 @@ void launch_eval(const EvalArgs &A, int mask, unsigned grid, hipStream_t s) {
 
 }  // namespace
 
+// Scratch of query_order_into for nq queries: the Morton keys, the sort's
+// second key and value buffers and its histogram / scan space, each aligned to
+// 256 bytes.
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+size_t query_order_scratch_bytes(int64_t nq) {
+    const size_t n = (size_t)std::max<int64_t>(nq, 1);
+    return 2 * align256(n * sizeof(uint64_t)) + align256(n * sizeof(uint32_t)) +
+           align256(radix_sort_temp_bytes(nq));
+}
+
 // Morton order of the queries in the scene box enlarged by half its extent on
-// every side (queries outside clamp to the boundary cells).  With idx, only the
-// n queries idx[0..n) are ordered and perm receives those indices sorted.
-int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s,
-                const uint32_t *idx) {
+// every side (queries outside clamp to the boundary cells), with the scratch
+// given by the caller (query_order_scratch_bytes(nq) bytes, 256-aligned).
+// With idx, only the n queries idx[0..n) are ordered and perm receives those
+// indices sorted.
+int query_order_into(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, void *scratch,
+                     hipStream_t s, const uint32_t *idx) {
     if (nq <= 0) return SD_OK;
-    uint64_t *keys, *keys2;
-    uint32_t *vals2;
-    char *temp;
-    size_t tb = radix_sort_temp_bytes(nq);
-    AsyncScratch tmp(s);
-    SD_TRY(tmp.alloc(&keys, nq));
-    SD_TRY(tmp.alloc(&keys2, nq));
-    SD_TRY(tmp.alloc(&vals2, nq));
-    SD_TRY(tmp.alloc(&temp, (int64_t)tb));
+    char *p = static_cast<char *>(scratch);
+    const size_t n = (size_t)nq;
+    uint64_t *keys = reinterpret_cast<uint64_t *>(p);
+    p += align256(n * sizeof(uint64_t));
+    uint64_t *keys2 = reinterpret_cast<uint64_t *>(p);
+    p += align256(n * sizeof(uint64_t));
+    uint32_t *vals2 = reinterpret_cast<uint32_t *>(p);
+    p += align256(n * sizeof(uint32_t));
     float ext[3], lo[3];
     for (int a = 0; a < 3; ++a) {
         float e = std::max(sc->box[3 + a] - sc->box[a], 1e-6f);
@@ -1375,8 +1387,71 @@ int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, 
     unsigned grid = (unsigned)((nq + kB - 1) / kB);
     hipLaunchKernelGGL(k_query_keys, dim3(grid), dim3(kB), 0, s, Q, idx, nq, lo[0], lo[1], lo[2],
                        1.f / ext[0], 1.f / ext[1], 1.f / ext[2], keys, perm);
-    SD_TRY(radix_sort_pairs(keys, perm, keys2, vals2, nq, 30, temp, s));
+    SD_TRY(radix_sort_pairs(keys, perm, keys2, vals2, nq, 30, p, s));
     return SD_OK;
+}
+
+// query_order_into with stream-ordered scratch of its own
+int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s,
+                const uint32_t *idx) {
+    if (nq <= 0) return SD_OK;
+    char *scratch;
+    AsyncScratch tmp(s);
+    SD_TRY(tmp.alloc(&scratch, (int64_t)query_order_scratch_bytes(nq)));
+    return query_order_into(sc, Q, nq, perm, scratch, s, idx);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free evaluation: the query order's scratch lives in this
+// file-scope device array (one copy per GPU the library runs on, held until
+// the process ends).  Host code must not use the array's name as a device
+// address: its address on each device comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxQ = SD_NOALLOC_MAX_QUERIES;
+constexpr size_t kNoAllocBytes =
+    4 * kNoAllocMaxQ + 2 * 8 * kNoAllocMaxQ + 4 * kNoAllocMaxQ + (size_t)(4 << 20);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static int noalloc_scratch(void **out) {
+    static std::mutex mu;
+    static void *ptr[64] = {};
+    int dev = 0;
+    SD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(SD_EUNSUPPORTED, "sd_eval_grad_noalloc: device index above 63");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SD_EHIP, std::string("sd_eval_grad_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return SD_OK;
+}
+
+int eval_grad_noalloc(const sd_scene *sc, const float *Q, int64_t nq, const sd_params *p, float *d_out,
+                      float *g_out, hipStream_t s) {
+    if (nq > kNoAllocMaxQ)
+        return fail(SD_EINVAL, "sd_eval_grad_noalloc: nQ = " + std::to_string(nq) + " exceeds the limit of " +
+                                   std::to_string(kNoAllocMaxQ) + " queries per call");
+    if (nq == 0) return SD_OK;
+    sd_params q = *p;
+    const uint32_t *perm = nullptr;
+    // the same ordering rule as sd_eval_grad: Morton order from 4096 queries on
+    if (!(p->flags & SD_NO_QUERY_SORT) && nq >= 4096 && sc->n_nodes[0] + sc->n_nodes[1] + sc->n_nodes[2] > 0) {
+        void *base;
+        SD_TRY(noalloc_scratch(&base));
+        uint32_t *pm = static_cast<uint32_t *>(base);
+        void *rest = static_cast<char *>(base) + align256((size_t)nq * sizeof(uint32_t));
+        if (align256((size_t)nq * 4) + query_order_scratch_bytes(nq) > kNoAllocBytes)
+            return fail(SD_EHIP, "sd_eval_grad_noalloc: scratch layout exceeds the static array");
+        SD_TRY(query_order_into(sc, Q, nq, pm, rest, s, nullptr));
+        perm = pm;
+    }
+    q.flags |= SD_NO_QUERY_SORT;
+    return eval_dispatch(sc, Q, perm, nq, &q, d_out, g_out, nullptr, false, s);
 }
 
 // Leaf evaluation mode: 1 = wave-cooperative leaf stage (default), 0 = each

@@ -155,6 +155,10 @@ namespace sd {
 // With idx, only the queries idx[0..nq) are ordered (perm gets those indices).
 int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s,
                 const uint32_t *idx = nullptr);
+// value + gradient with the query order's scratch in a static device array
+// (no allocation; at most SD_NOALLOC_MAX_QUERIES queries) (eval.hip)
+int eval_grad_noalloc(const sd_scene *sc, const float *Q, int64_t nq, const sd_params *p, float *d_out,
+                      float *g_out, hipStream_t s);
 // nthr >= 0 with perm_in: nthr threads evaluate the queries perm_in[0..nthr)
 // out of nq; results land at the original query indices.
 // value + gradient for edge (nv = 2) or triangle (nv = 3) query primitives (eval.hip)
