@@ -1,16 +1,21 @@
 """Smooth-distance value+gradient throughput on one MI355X.
 
-Workload: the bumpy level-7 icosphere (327,680 triangles, 163,842 vertices,
-radial sinusoid bumps) with 1,000,000 FP32 queries, half uniform in
-[-1.5, 1.5]^3 and half within +-0.02 of the surface along face normals;
-alpha = 50, beta = 0.5 (Barnes-Hut), the paper's blending weights.
+Headline workload (the largest single-GPU configuration): a 20M-point noisy
+fBm terrain over [-1, 1]^2, a 1M-triangle torus above it and a 199,200-edge
+hemispherical net; 32M FP32 queries uniform in the scene box enlarged by 10 %;
+alpha = 100, beta = 0.5 (Barnes-Hut), the paper's blending weights, value and
+gradient.  One step = Morton ordering of the queries + Alg. 1/Alg. 2 traversal
+with value and gradient for every query (sd_query_order +
+sd_eval_grad_ordered), inputs resident in HBM.  The hierarchy build is timed
+separately.
 
-One step = Morton ordering of the queries + Alg. 1/Alg. 2 traversal with
-value and gradient for every query (sd_query_order + sd_eval_grad_ordered),
-inputs resident in HBM.  The hierarchy build is timed separately (build_ms).
+Further legs (extra keys of the same JSON line): the 2,000-point sphere
+(Barnes-Hut against brute force), the bumpy level-7 icosphere at alpha 50 and
+500, the alpha sweep 10 / 100 / 1000 / 5000 on the headline scene, the learned
+surrogate, the rigid-body street step; --headline-only skips them.
 
-Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
-the library runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is not supported: the library runs on one
+GPU.
 """
 import argparse
 import hashlib
@@ -27,16 +32,17 @@ HBM_PEAK_GBS = 8000.0
 # disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 78.6
 ALU_PEAK_PACKED_TFLOPS = 157.3
-# algorithmic FLOPs per unit of work, value + gradient, counted from the kernel's arithmetic:
-F_QUERY = 50        # load, seed bookkeeping, finalisation
-F_NODE = 26         # box distance, box diagonal, opening and pruning tests
-F_FAR = 23          # sqrt, rcp, direction, exponent, FP64 sums (1 add + 3 FMA)
-F_TRI_LEAF = 624    # distance + region, de Casteljau weight, gradient, FP64 sums
 METRIC = "smooth-distance+grad queries/s on 1 MI355X: BH vs surrogate at ≤1e-5 rel / 1e-3 abs"
-# algorithmic bytes per unit of work: query in, outputs out, node and leaf records read
-B_QUERY = 12 + 16 + 4        # query in, value + gradient out, order index
-B_NODE = 32                  # one hierarchy node record
-B_TRI_LEAF = 48              # one triangle leaf record
+# Algorithmic work per query, value + gradient (not the instructions the
+# kernel issues):
+#   FLOPs = 20 per node visited + 25 per far-field term + 30 / 80 / 200 per
+#           exact point / edge / triangle leaf term
+#   bytes = 12 (query) + 16 (value, gradient) + 32 per node record
+#           + 12 / 32 / 40 per point / edge / triangle leaf record
+F_NODE, F_FAR, F_LEAF = 20, 25, (30, 80, 200)
+B_QUERY, B_NODE, B_LEAF = 12 + 16, 32, (12, 32, 40)
+ICO_ALPHAS = (50.0, 500.0)
+SWEEP_ALPHAS = (10.0, 100.0, 1000.0, 5000.0)
 
 
 def _progress(msg):
@@ -65,33 +71,124 @@ def _traffic(kernel_src, name, units):
     return t["hbm_bytes_per_launch"] / t["units_per_launch"] * units
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _work(np, cnt):
+    """Mean per-query work from the by-class counters (n x 5: nodes, far
+    terms, point / edge / triangle leaves) -> (work dict, FLOPs, bytes)."""
+    m = [float(x) for x in cnt.mean(0)]
+    flops = F_NODE * m[0] + F_FAR * m[1] + sum(f * x for f, x in zip(F_LEAF, m[2:5]))
+    nbytes = B_QUERY + B_NODE * m[0] + sum(b * x for b, x in zip(B_LEAF, m[2:5]))
+    k = min(len(cnt), 200_000)
+    p99 = np.quantile(cnt[:k], 0.99, axis=0)
+    work = {"nodes": m[0], "far_terms": m[1], "point_leaves": m[2], "edge_leaves": m[3],
+            "triangle_leaves": m[4], "p99_nodes": float(p99[0]), "p99_far": float(p99[1]),
+            "p99_leaves": float(np.quantile(cnt[:k, 2:5].sum(1), 0.99))}
+    return work, flops, nbytes
+
+
+def _roofline(kernel, n, kernel_ms, flops_q, bytes_q, traffic):
+    t = kernel_ms * 1e-3
+    tflops = n * flops_q / t / 1e12
+    out = {"bound": "alu", "kernel": kernel, "achieved": tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
+           "peak_note": "FP32 vector FMA rate of code built without packed-FP32 instructions "
+                        "(256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz); the FP64 vector rate is the same",
+           "frac_of_packed_peak": tflops / ALU_PEAK_PACKED_TFLOPS,
+           "flops_per_query": flops_q,
+           "flop_model": "20 per node + 25 per far-field term + 30/80/200 per point/edge/triangle leaf",
+           "kernel_ms": kernel_ms,
+           "algorithmic_bytes": {"per_query": bytes_q, "GB_per_s": n * bytes_q / t / 1e9,
+                                 "note": "node and leaf records as read by the algorithm; most are served "
+                                         "by L1/L2/MALL, so this is not an HBM figure"}}
+    if traffic is not None:
+        gbs = traffic / t / 1e9
+        out["hbm_measured"] = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def _timed_steps(torch, step, steps, warmup):
+    """warmup untimed steps, then `steps` timed ones between two events on the
+    current stream; per-step events around the traversal (stage 1 -> 2)."""
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for k in range(steps):
+        step(ev[k])
+    e1.record(s)
+    torch.cuda.synchronize()
+    total = e0.elapsed_time(e1)
+    order = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    trav = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    return total / steps, order, trav
+
+
+def _ordered_step(api, scene, Q, perm, d, g, alpha, beta, flags=0):
+    def step(evs):
+        if evs: evs[0].record()
+        api.sd_query_order(scene, Q, out=perm)
+        if evs: evs[1].record()
+        api.sd_eval_grad_ordered(scene, Q, perm, alpha, beta, flags=flags, out=d, grad_out=g)
+        if evs: evs[2].record()
+    return step
+
+
+def _parity(np, O, osc, trees, Qs, d, g, alpha, beta, floor):
+    """Default outputs d, g of the sample Qs against the oracle (Barnes-Hut on
+    the exported hierarchies, FP32 opening decisions), and d <= d_min against
+    the oracle's exact nearest distance."""
+    t0 = time.perf_counter()
+    dr, gr, _ = O.barnes_hut(osc, trees, Qs, alpha, beta, cut_f32=True)
+    dt = time.perf_counter() - t0
+    dm = O.dmin_tree(osc, trees, Qs)
+    ev = O.value_error(d, dr, floor)
+    eg = O.grad_error(g, gr)
+    return {"n": int(len(Qs)), "max_err_vs_oracle": float(ev.max()), "max_grad_err_vs_oracle": float(eg.max()),
+            "p999_err_vs_oracle": float(np.quantile(ev, 0.999)),
+            "metric": "|d - d_oracle| / max(|d_oracle|, 1e-3 scene diagonal); gradient "
+                      "|g - g_oracle| / max(|g_oracle|, 1e-2); default (conservative) output",
+            "gate_1e-5_met": bool(ev.max() <= 1e-5 and eg.max() <= 1e-5),
+            "conservative_violations": int(np.sum(d.astype(np.float64) > dm))}, dt
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--alpha", type=float, default=50.0)
+    ap.add_argument("--alpha", type=float, default=100.0)
     ap.add_argument("--beta", type=float, default=0.5)
-    ap.add_argument("--level", type=int, default=7)
-    ap.add_argument("--nq", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="queries of the workload timed on the FP64 oracle (0: all of them)")
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="headline scene size relative to 20M points, 1M triangles, 200k edges, 32M queries")
+    ap.add_argument("--cpu-sample", type=int, default=100_000,
+                    help="queries of the headline workload timed on the FP64 oracle and checked against it")
+    ap.add_argument("--headline-only", action="store_true", help="only the headline workload (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate comparison")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid-body street workload")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the alpha sweep on the headline scene")
     ap.add_argument("--rigid-steps", type=int, default=5)
-    ap.add_argument("--sweep", action="store_true",
-                    help="also run the alpha / precision sweep on the terrain + mesh scene")
-    ap.add_argument("--sweep-scale", type=float, default=1.0,
-                    help="size of the sweep scene relative to 20M points, 1M triangles, 200k edges, 32M queries")
-    ap.add_argument("--sweep-oracle", type=int, default=2000,
-                    help="queries of the sweep checked against the FP64 oracle (brute-force minimum distance "
-                         "over every primitive, Barnes-Hut on the exported hierarchies)")
+    ap.add_argument("--sweep-oracle", type=int, default=20_000,
+                    help="queries of each sweep alpha checked against the oracle")
     ap.add_argument("--beta-ablation", action="store_true",
                     help="sphere-trace renders of vertex, edge and triangle scenes over beta (Sec. 4.3 analogue)")
     ap.add_argument("--ablation-res", type=int, default=256, help="image side of the beta ablation renders")
     ap.add_argument("--prims", action="store_true",
-                    help="edges and triangles as query primitives on the benchmark scene (Sec. 3.4)")
+                    help="edges and triangles as query primitives on the icosphere scene (Sec. 3.4)")
     ap.add_argument("--contact", action="store_true",
                     help="rigid-body contact steps of the street body dropped on the street (Sec. 4.5)")
     ap.add_argument("--switch-study", action="store_true",
@@ -126,179 +223,101 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    _progress("icosphere scene and queries")
-    t_gen = time.time()
-    sc = scenes.bumpy_icosphere(level=args.level, seed=2)
-    Q = scenes.icosphere_queries(sc, args.nq, seed_box=3, seed_surf=4)
-    t_gen = time.time() - t_gen
+    _progress("terrain scene and queries")
+    sc = scenes.terrain_scene(args.scale)
+    nq = max(int(round(32_000_000 * args.scale)), 1000)
+    Q = scenes.terrain_queries(sc, nq, seed=10)
+    cnt_cls = sc.counts()
     V = torch.as_tensor(sc.V, device=dev)
+    P = torch.as_tensor(sc.P, device=dev)
+    E = torch.as_tensor(sc.E, device=dev)
     T = torch.as_tensor(sc.T, device=dev)
     Qd = torch.as_tensor(Q, device=dev)
     torch.cuda.synchronize()
 
     _progress("hierarchy build")
-    # hierarchy build (a1-a3), timed on its own
     builds = []
     for _ in range(2):
         t0 = time.perf_counter()
-        scene = api.sd_build_bvh(V, T=T)
+        scene = api.sd_build_bvh(V, P=P, E=E, T=T)
         torch.cuda.synchronize()
         builds.append((time.perf_counter() - t0) * 1e3)
-    info = scene.info()
+    del V, P, E, T
 
-    n = args.nq
-    perm = torch.empty(n, dtype=torch.int32, device=dev)
-    d = torch.empty(n, dtype=torch.float32, device=dev)
-    g = torch.empty((n, 3), dtype=torch.float32, device=dev)
-
-    def step():
-        api.sd_query_order(scene, Qd, out=perm)
-        api.sd_eval_grad_ordered(scene, Qd, perm, args.alpha, args.beta, out=d, grad_out=g)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    s = torch.cuda.current_stream()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(s)
-    for k in range(args.steps):
-        ev[k][0].record(s)
-        api.sd_query_order(scene, Qd, out=perm)
-        ev[k][1].record(s)
-        api.sd_eval_grad_ordered(scene, Qd, perm, args.alpha, args.beta, out=d, grad_out=g)
-        ev[k][2].record(s)
-    e1.record(s)
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    ms_step = total_ms / args.steps
-    order_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    eval_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))   # the traversal kernel alone
-    qps = n / (ms_step * 1e-3)
-
-    # the same step visiting every node of Alg. 1's cut (no negligible-subtree skipping)
-    e2 = torch.cuda.Event(enable_timing=True)
-    e3 = torch.cuda.Event(enable_timing=True)
-    e2.record(s)
-    for k in range(args.steps):
-        api.sd_query_order(scene, Qd, out=perm)
-        api.sd_eval_grad_ordered(scene, Qd, perm, args.alpha, args.beta, flags=api.SD_NO_PRUNE,
-                                 out=d, grad_out=g)
-    e3.record(s)
-    torch.cuda.synchronize()
-    ms_step_noprune = e2.elapsed_time(e3) / args.steps
-    cnt_np = api.sd_eval_counters(scene, Qd, args.alpha, args.beta, flags=api.SD_NO_PRUNE).double()
-    api.sd_query_order(scene, Qd, out=perm)
-    api.sd_eval_grad_ordered(scene, Qd, perm, args.alpha, args.beta, out=d, grad_out=g)
-
-    # work counters on the same inputs -> algorithmic bytes
-    cnt = api.sd_eval_counters(scene, Qd, args.alpha, args.beta).double()
-    nodes, far, leaves = [float(x) for x in cnt.mean(0).cpu()]
-    p99 = [float(x) for x in torch.quantile(cnt[:200000], 0.99, dim=0).cpu()]
-    bytes_per_query = B_QUERY + B_NODE * nodes + B_TRI_LEAF * leaves
-    achieved = n * bytes_per_query / (eval_ms * 1e-3) / 1e9
-    flops_per_query = F_QUERY + F_NODE * nodes + F_FAR * far + F_TRI_LEAF * leaves
-    tflops = n * flops_per_query / (eval_ms * 1e-3) / 1e12
-    traffic = _traffic(os.path.join(ROOT, "paper_2108_10480_amd", "csrc", "eval.hip"),
-                       "traffic_k_eval_icosphere_l7_1M.json", n)
-
+    _progress("headline steps")
+    perm = torch.empty(nq, dtype=torch.int32, device=dev)
+    d = torch.empty(nq, dtype=torch.float32, device=dev)
+    g = torch.empty((nq, 3), dtype=torch.float32, device=dev)
+    ms_step, order_ms, eval_ms = _timed_steps(torch, _ordered_step(api, scene, Qd, perm, d, g, args.alpha,
+                                                                     args.beta), args.steps, args.warmup)
+    qps = nq / (ms_step * 1e-3)
+    workload = (f"terrain {cnt_cls[0]} points (fBm heightfield + noise) + torus {cnt_cls[2]} triangles + "
+                f"hemisphere net {cnt_cls[1]} edges; {nq} queries uniform in the scene box enlarged by 10 %; "
+                f"alpha={args.alpha:g}, beta={args.beta:g}, Barnes-Hut, value+gradient")
     out = {
-        "metric": METRIC,
-        "value": qps,
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"bumpy icosphere level {args.level} ({info['n_prims'][2]} triangles), "
-                        f"{n} queries (half uniform in [-1.5,1.5]^3, half within 0.02 of the "
-                        f"surface), alpha={args.alpha:g}, beta={args.beta:g}, Barnes-Hut, "
-                        "value+gradient",
-            "mode": "barnes_hut",
-            "n_triangles": info["n_prims"][2],
-            "n_queries": n,
-            "alpha": args.alpha,
-            "beta": args.beta,
-        },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_eval (Barnes-Hut traversal, value+gradient)",
-            "achieved": tflops,
-            "peak": ALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": tflops / ALU_PEAK_TFLOPS,
-            "frac_of_packed_peak": tflops / ALU_PEAK_PACKED_TFLOPS,
-            "traffic": traffic,
-            "flops_per_query": flops_per_query,
-            "kernel_ms": eval_ms,
-            "hbm_algorithmic": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                "frac": achieved / HBM_PEAK_GBS,
-                                "bytes_per_query": bytes_per_query},
-        },
+        "metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": workload, "mode": "barnes_hut", "n_points": cnt_cls[0], "n_edges": cnt_cls[1],
+                   "n_triangles": cnt_cls[2], "n_queries": nq, "alpha": args.alpha, "beta": args.beta},
         "stages_ms": {"query_order": order_ms, "traversal": eval_ms, "build": min(builds)},
-        "work_per_query": {"nodes": nodes, "far_terms": far, "leaves": leaves,
-                           "p99_nodes": p99[0], "p99_far": p99[1], "p99_leaves": p99[2]},
-        "no_prune": {"value": n / (ms_step_noprune * 1e-3), "ms_per_step": ms_step_noprune,
-                     "nodes": float(cnt_np[:, 0].mean()), "far_terms": float(cnt_np[:, 1].mean()),
-                     "leaves": float(cnt_np[:, 2].mean())},
     }
+    if args.headline_only:
+        print(json.dumps(out))
+        return
 
+    _progress("work counters")
+    cnt = api.sd_eval_counters(scene, Qd, args.alpha, args.beta, flags=api.SD_COUNTERS_BY_CLASS).cpu().numpy()
+    work, flops_q, bytes_q = _work(np, cnt)
+    del cnt
+    out["work_per_query"] = work
+    out["roofline"] = _roofline("k_eval (Barnes-Hut traversal, value+gradient, three classes)", nq, eval_ms,
+                                flops_q, bytes_q,
+                                _traffic(os.path.join(ROOT, "paper_2108_10480_amd", "csrc", "eval.hip"),
+                                         "traffic_k_eval_terrain_32M.json", nq))
+    lo, hi = scenes.scene_aabb(sc)
+    floor = 1e-3 * float(np.linalg.norm(hi - lo))
+    O = osc = trees = None
     if not args.no_cpu_baseline:
         _progress("FP64 oracle on the host (cpu baseline, parity sample)")
         from oracle import oracle as O
+        osc = O.OracleScene(sc.V, P=sc.P, E=sc.E, T=sc.T)
+        trees = [O.OracleTree(*api.sd_export_bvh(scene, c)) for c in range(3)]
         rng = np.random.default_rng(123)
-        k = n if args.cpu_sample <= 0 else min(args.cpu_sample, n)
-        idx = np.sort(rng.choice(n, size=k, replace=False)) if k < n else np.arange(n)
-        trees = [None, None, O.OracleTree(*api.sd_export_bvh(scene, 2))]
-        osc = O.OracleScene(sc.V, T=sc.T)
-        Qs = Q[idx].astype(np.float64)
-        t0 = time.perf_counter()
-        dr, gr, st = O.barnes_hut(osc, trees, Qs, args.alpha, args.beta, cut_f32=True)
-        dt = time.perf_counter() - t0
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        d_s = d.cpu().numpy()[idx]
-        dm_floor = 1e-3 * float(np.linalg.norm(sc.V.max(0) - sc.V.min(0)))
-        err = O.value_error(d_s, dr, dm_floor)
+        k = min(args.cpu_sample, nq)
+        idx = np.sort(rng.choice(nq, size=k, replace=False))
+        idx_d = torch.as_tensor(idx, device=dev)
+        par, dt = _parity(np, O, osc, trees, Q[idx].astype(np.float64), d[idx_d].cpu().numpy(),
+                          g[idx_d].cpu().numpy(), args.alpha, args.beta, floor)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = {
-            "value": len(idx) / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(idx)} queries of the same workload ({'all' if len(idx) == n else 'random'}), "
-                      f"FP64 Barnes-Hut oracle on the exported hierarchy ({dt:.1f} s)",
-        }
-        # the same queries without the conservative downward rounding: the
-        # plain FP32 arithmetic against the oracle (value and gradient)
-        dp, gp = api.sd_eval_grad(scene, Qd, args.alpha, args.beta, flags=api.SD_NO_CONSERVATIVE_ROUNDING)
-        torch.cuda.synchronize()
-        idx_d = torch.as_tensor(idx, device="cuda")
-        err_p = O.value_error(dp[idx_d].cpu().numpy(), dr, dm_floor)
-        err_g = O.grad_error(gp[idx_d].cpu().numpy(), gr)
-        out["parity_sample"] = {"max_err_vs_oracle": float(err.max()),
-                                "metric": "|d - d_oracle| / max(|d_oracle|, 1e-3 scene diagonal); d includes "
-                                          "the default downward rounding of the conservative mode",
-                                "max_err_plain_vs_oracle": float(err_p.max()),
-                                "max_grad_err_plain_vs_oracle": float(err_g.max()),
-                                "grad_metric": "|g - g_oracle| / max(|g_oracle|, 1e-2)",
-                                "conservative_violations": int(np.sum(d_s > dr)),
-                                "n": len(d_s)}
+            "value": k / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} random queries of the headline workload, FP64 Barnes-Hut oracle on the exported "
+                      f"hierarchies (Alg. 1/Alg. 2, every term in FP64), {dt:.1f} s",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+        out["parity_sample"] = par
+    if not args.no_sweep:
+        out["alpha_sweep"] = alpha_sweep_leg(args, np, torch, api, scene, Qd, perm, d, g, O, osc, trees, Q,
+                                             floor)
+    del d, g, perm
+    if not args.no_cpu_baseline:
+        del trees
+    scene.free()
+    del Qd
+
+    out["point_sphere"] = point_sphere_leg(args, np, torch, api, scenes)
+    ico, ico_sc, ico_scene = icosphere_leg(args, np, torch, api, scenes)
+    out["icosphere"] = ico
     if not args.no_surrogate:
         _progress("surrogate")
-        out["surrogate"] = surrogate_leg(args, sc, scene, np, torch, api, scenes)
+        out["surrogate"] = surrogate_leg(args, ico_sc, ico_scene, np, torch, api, scenes)
+    if args.prims:
+        _progress("query primitives")
+        out["query_primitives"] = prims_leg(args, np, torch, api, scenes, ico_sc, ico_scene)
+    ico_scene.free()
     if not args.no_rigid:
         _progress("rigid")
         out["rigid"] = rigid_leg(args, np, torch, api, scenes)
-    if args.sweep:
-        _progress("precision sweep")
-        out["precision_sweep"] = sweep_leg(args, np, torch, api, scenes)
-    if args.prims:
-        _progress("query primitives")
-        out["query_primitives"] = prims_leg(args, np, torch, api, scenes, sc, scene)
     if args.contact:
         _progress("contact")
         out["contact"] = contact_leg(args, np, torch, api, scenes)
@@ -309,6 +328,132 @@ def main():
         _progress("switch study")
         out["switch_study"] = switch_study_leg(args, np, torch, api, scenes)
     print(json.dumps(out))
+
+
+def alpha_sweep_leg(args, np, torch, api, scene, Qd, perm, d, g, O, osc, trees, Q, floor):
+    """alpha = 10, 100, 1000, 5000 on the headline scene and queries:
+    throughput (ordering + traversal), work per query and, on a random
+    sample, the default output against the oracle and d <= d_min."""
+    nq = len(Q)
+    rng = np.random.default_rng(456)
+    k = min(args.sweep_oracle, nq)
+    idx = np.sort(rng.choice(nq, size=k, replace=False))
+    idx_d = torch.as_tensor(idx, device="cuda")
+    Qs = Q[idx].astype(np.float64)
+    res = {"workload": "headline scene and queries; oracle sample of "
+                       f"{k} random queries per alpha", "alphas": {}}
+    for alpha in SWEEP_ALPHAS:
+        _progress(f"alpha sweep: {alpha:g}")
+        ms, _, trav = _timed_steps(torch, _ordered_step(api, scene, Qd, perm, d, g, alpha, args.beta), 3, 1)
+        c = api.sd_eval_counters(scene, Qd[idx_d], alpha, args.beta, flags=api.SD_COUNTERS_BY_CLASS).cpu().numpy()
+        work, flops_q, _ = _work(np, c)
+        row = {"queries_per_s": nq / (ms * 1e-3), "ms_per_step": ms, "traversal_ms": trav,
+               "roofline_frac": nq * flops_q / (trav * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+               "work_per_query_on_sample": {k2: work[k2] for k2 in ("nodes", "far_terms", "point_leaves",
+                                                                    "edge_leaves", "triangle_leaves")}}
+        if O is not None:
+            row["parity_sample"], _ = _parity(np, O, osc, trees, Qs, d[idx_d].cpu().numpy(), g[idx_d].cpu().numpy(),
+                                              alpha, args.beta, floor)
+        res["alphas"][f"{alpha:g}"] = row
+    return res
+
+
+def point_sphere_leg(args, np, torch, api, scenes):
+    """The 2,000-point sphere (radial noise 0.005) with 10,000 uniform queries,
+    alpha = 100: Barnes-Hut (beta 0.5) against brute force (beta 0, the
+    traversal opening every node, and the all-pairs kernel); each against the
+    oracle on every query."""
+    _progress("point sphere")
+    sc, Q = scenes.point_sphere(2000, 10000)
+    scene = api.upload_scene(sc)
+    Qd = torch.as_tensor(Q, device="cuda")
+    alpha = 100.0
+    n = len(Q)
+
+    def timed(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            r = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps, r
+
+    ms_bh, (d_bh, g_bh) = timed(lambda: api.sd_eval_grad(scene, Qd, alpha, args.beta))
+    ms_b0, (d_b0, g_b0) = timed(lambda: api.sd_eval_grad(scene, Qd, alpha, 0.0))
+    ms_all, (d_all, g_all) = timed(lambda: api.sd_eval_brute(scene, Qd, alpha))
+    res = {"workload": f"{len(sc.P)} points on the unit sphere (radial N(0, 0.005^2)), {n} queries uniform in "
+                       f"[-1.5, 1.5]^3, alpha={alpha:g}, value+gradient",
+           "barnes_hut": {"beta": args.beta, "queries_per_s": n / (ms_bh * 1e-3), "ms": ms_bh},
+           "brute_force_traversal": {"beta": 0.0, "queries_per_s": n / (ms_b0 * 1e-3), "ms": ms_b0},
+           "brute_force_all_pairs": {"queries_per_s": n / (ms_all * 1e-3), "ms": ms_all}}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        osc = O.OracleScene(sc.V, P=sc.P)
+        trees = [O.OracleTree(*api.sd_export_bvh(scene, 0)), None, None]
+        lo, hi = scenes.scene_aabb(sc)
+        floor = 1e-3 * float(np.linalg.norm(hi - lo))
+        Q64 = Q.astype(np.float64)
+        res["barnes_hut"]["parity"], _ = _parity(np, O, osc, trees, Q64, d_bh.cpu().numpy(), g_bh.cpu().numpy(),
+                                                 alpha, args.beta, floor)
+        dr, gr, dm = O.brute(osc, Q64, alpha)
+        for key, (dd, gg) in (("brute_force_traversal", (d_b0, g_b0)), ("brute_force_all_pairs", (d_all, g_all))):
+            dd, gg = dd.cpu().numpy(), gg.cpu().numpy()
+            res[key]["parity"] = {"n": n, "max_err_vs_oracle": float(O.value_error(dd, dr, floor).max()),
+                                  "max_grad_err_vs_oracle": float(O.grad_error(gg, gr).max()),
+                                  "conservative_violations": int(np.sum(dd.astype(np.float64) > dm))}
+        # Barnes-Hut against the exact smooth distance: the price of the far field
+        eb = np.abs(d_bh.cpu().numpy() - dr)
+        res["barnes_hut"]["vs_exact_smooth_distance"] = {"max_abs": float(eb.max()), "mean_abs": float(eb.mean())}
+    scene.free()
+    return res
+
+
+def icosphere_leg(args, np, torch, api, scenes):
+    """The bumpy level-7 icosphere (327,680 triangles) with 1M queries (half
+    uniform in [-1.5, 1.5]^3, half within 0.02 of the surface) at alpha 50
+    and 500: throughput, work, roofline fraction, and a 200,000-query sample
+    of the default output against the oracle with d <= d_min."""
+    _progress("icosphere")
+    sc = scenes.bumpy_icosphere(level=7, seed=2)
+    n = 1_000_000
+    Q = scenes.icosphere_queries(sc, n, seed_box=3, seed_surf=4)
+    t0 = time.perf_counter()
+    scene = api.upload_scene(sc)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    Qd = torch.as_tensor(Q, device="cuda")
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    d = torch.empty(n, device="cuda")
+    g = torch.empty((n, 3), device="cuda")
+    res = {"workload": f"bumpy icosphere level 7 ({len(sc.T)} triangles), {n} queries (half uniform in "
+                       f"[-1.5,1.5]^3, half within 0.02 of the surface), beta={args.beta:g}, value+gradient",
+           "build_ms": build_ms, "alphas": {}}
+    O = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        osc = O.OracleScene(sc.V, T=sc.T)
+        trees = [None, None, O.OracleTree(*api.sd_export_bvh(scene, 2))]
+        lo, hi = scenes.scene_aabb(sc)
+        floor = 1e-3 * float(np.linalg.norm(hi - lo))
+        idx = np.sort(np.random.default_rng(789).choice(n, size=200_000, replace=False))
+        idx_d = torch.as_tensor(idx, device="cuda")
+    for alpha in ICO_ALPHAS:
+        ms, order_ms, trav = _timed_steps(torch, _ordered_step(api, scene, Qd, perm, d, g, alpha, args.beta), 20, 3)
+        c = api.sd_eval_counters(scene, Qd, alpha, args.beta, flags=api.SD_COUNTERS_BY_CLASS).cpu().numpy()
+        work, flops_q, bytes_q = _work(np, c)
+        row = {"queries_per_s": n / (ms * 1e-3), "ms_per_step": ms, "query_order_ms": order_ms,
+               "traversal_ms": trav, "work_per_query": work,
+               "roofline": _roofline("k_eval (triangles)", n, trav, flops_q, bytes_q,
+                                     _traffic(os.path.join(ROOT, "paper_2108_10480_amd", "csrc", "eval.hip"),
+                                              f"traffic_k_eval_icosphere_l7_1M_a{alpha:g}.json", n))}
+        if O is not None:
+            row["parity_sample"], _ = _parity(np, O, osc, trees, Q[idx].astype(np.float64), d[idx_d].cpu().numpy(),
+                                              g[idx_d].cpu().numpy(), alpha, args.beta, floor)
+        res["alphas"][f"{alpha:g}"] = row
+    return res, sc, scene
 
 
 def _camera_rays(np, res, eye, fov_deg=40.0):
@@ -327,25 +472,26 @@ def _camera_rays(np, res, eye, fov_deg=40.0):
 
 
 def prims_leg(args, np, torch, api, scenes, sc, scene):
-    """Edges and triangles as query primitives (Sec. 3.4) on the benchmark
+    """Edges and triangles as query primitives (Sec. 3.4) on the icosphere
     scene: 1M small random segments / triangles placed like the point queries
-    (half uniform in the box, half near the surface), alpha and beta as the
-    headline; throughput and an oracle sample."""
+    (half uniform in the box, half near the surface), alpha 50, beta 0.5;
+    throughput and an oracle sample."""
     rng = np.random.default_rng(31)
     n = 1_000_000
+    alpha, beta = ICO_ALPHAS[0], args.beta
     C = scenes.icosphere_queries(sc, n, seed_box=32, seed_surf=33)
-    out = {"workload": f"bumpy icosphere level {args.level} ({len(sc.T)} triangles), {n} query primitives "
+    out = {"workload": f"bumpy icosphere level 7 ({len(sc.T)} triangles), {n} query primitives "
                        f"(random segments / triangles of size ~0.02 at the point-query positions), "
-                       f"alpha={args.alpha:g}, beta={args.beta:g}, value+gradient"}
+                       f"alpha={alpha:g}, beta={beta:g}, value+gradient"}
     for nv, name in ((2, "edges"), (3, "triangles")):
         G = (C[:, None, :] + rng.normal(size=(n, nv, 3)) * 0.01).astype(np.float32)
         Gd = torch.as_tensor(G, device="cuda")
-        api.sd_eval_grad_prims(scene, Gd, args.alpha, args.beta)
+        api.sd_eval_grad_prims(scene, Gd, alpha, beta)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(3):
-            d, g = api.sd_eval_grad_prims(scene, Gd, args.alpha, args.beta)
+            d, g = api.sd_eval_grad_prims(scene, Gd, alpha, beta)
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / 3
@@ -355,11 +501,9 @@ def prims_leg(args, np, torch, api, scenes, sc, scene):
             idx = np.sort(rng.choice(n, 2000, replace=False))
             osc = O.OracleScene(sc.V, T=sc.T)
             trees = [None, None, O.OracleTree(*api.sd_export_bvh(scene, 2))]
-            dn, _ = api.sd_eval_grad_prims(scene, Gd[torch.as_tensor(idx, device="cuda")], args.alpha, args.beta,
-                                           flags=api.SD_NO_CONSERVATIVE_ROUNDING)
-            dr, _, _ = O.barnes_hut_prims(osc, trees, G[idx].astype(np.float64), args.alpha, args.beta,
-                                          cut_f32=True)
-            _, _, dm = O.brute_prims(osc, G[idx[:200]].astype(np.float64), args.alpha)
+            dn, _ = api.sd_eval_grad_prims(scene, Gd[torch.as_tensor(idx, device="cuda")], alpha, beta)
+            dr, _, _ = O.barnes_hut_prims(osc, trees, G[idx].astype(np.float64), alpha, beta, cut_f32=True)
+            _, _, dm = O.brute_prims(osc, G[idx[:200]].astype(np.float64), alpha)
             floor = 1e-3 * float(np.linalg.norm(sc.V.max(0) - sc.V.min(0)))
             e = O.value_error(dn.cpu().numpy(), dr, floor)
             row["parity_sample"] = {"n": len(idx), "max_err_vs_oracle": float(e.max()),
@@ -502,73 +646,6 @@ def switch_study_leg(args, np, torch, api, scenes):
             "gradient_cosine_min": float(cos.min()) if cos.size else None}
 
 
-def sweep_leg(args, np, torch, api, scenes):
-    """Alpha sweep on the terrain + mesh scene: throughput, and error against
-    the FP64 oracle (Barnes-Hut on the exported hierarchies) of the plain FP32
-    path and of the FP64 final logarithm, for alpha = 10, 100, 1000, 5000."""
-    beta = 0.5
-    sc = scenes.terrain_scene(args.sweep_scale)
-    t0 = time.perf_counter()
-    scene = api.upload_scene(sc)
-    torch.cuda.synchronize()
-    build_ms = (time.perf_counter() - t0) * 1e3
-    nq = max(int(32_000_000 * args.sweep_scale), 1000)
-    Q = torch.as_tensor(scenes.terrain_queries(sc, nq, seed=10), device="cuda")
-    perm = torch.empty(nq, dtype=torch.int32, device="cuda")
-    d = torch.empty(nq, device="cuda")
-    g = torch.empty((nq, 3), device="cuda")
-    n_or = max(min(args.sweep_oracle, nq), 1)
-    Qs = Q[:n_or].contiguous()
-    res = {"workload": f"terrain {sc.counts()[0]} points + torus {sc.counts()[2]} triangles + "
-                       f"hemisphere net {sc.counts()[1]} edges; {nq} queries in the box enlarged by 10 %, "
-                       f"beta={beta:g}; oracle subset: first {n_or} queries",
-           "build_ms": build_ms, "alphas": {}}
-    have_oracle = not args.no_cpu_baseline
-    if have_oracle:
-        from oracle import oracle as O
-        osc = O.OracleScene(sc.V, P=sc.P, E=sc.E, T=sc.T)
-        trees = [O.OracleTree(*api.sd_export_bvh(scene, c)) for c in range(3)]
-        lo, hi = scenes.scene_aabb(sc)
-        floor = 1e-3 * float(np.linalg.norm(hi - lo))
-    for alpha in (10.0, 100.0, 1000.0, 5000.0):
-        _progress(f"precision sweep: alpha {alpha:g}")
-        row = {}
-        for mode, fl in (("fp32", 0), ("fp64_root_log", api.SD_ROOTLOG_F64)):
-            def run():
-                api.sd_query_order(scene, Q, out=perm)
-                api.sd_eval_grad_ordered(scene, Q, perm, alpha, beta, flags=fl, out=d, grad_out=g)
-            run()
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(3):
-                run()
-            b.record()
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / 3
-            entry = {"queries_per_s": nq / (ms * 1e-3), "ms": ms}
-            if have_oracle:
-                dn, _ = api.sd_eval_grad(scene, Qs, alpha, beta, flags=fl | api.SD_NO_CONSERVATIVE_ROUNDING)
-                dc, _ = api.sd_eval_grad(scene, Qs, alpha, beta, flags=fl)
-                row.setdefault("_gpu", {})[mode] = (dn.cpu().numpy(), dc.cpu().numpy())
-            row[mode] = entry
-        if have_oracle:
-            Qh = Qs.cpu().numpy().astype(np.float64)
-            if "dmin" not in res:
-                _progress(f"precision sweep: brute-force minimum distance of {len(Qh)} queries on the host")
-                res["dmin"] = O.dmin(osc, Qh)
-            dr, _, st = O.barnes_hut(osc, trees, Qh, alpha, beta, cut_f32=True)
-            for mode, (dn, dc) in row.pop("_gpu").items():
-                e = O.value_error(dn, dr, floor)
-                row[mode]["max_err_vs_oracle"] = float(e.max())
-                row[mode]["median_err_vs_oracle"] = float(np.median(e))
-                row[mode]["conservative_violations"] = int(np.sum(dc > dr))
-            row["oracle_n"] = len(dr)
-        res["alphas"][f"{alpha:g}"] = row
-    res.pop("dmin", None)
-    return res
-
-
 def rigid_leg(args, np, torch, api, scenes):
     """Differentiable rigid-body step on the mixed street scene: 256 rigid
     transforms of a 25,000-vertex torus (6.4M queries) against 2M points,
@@ -685,7 +762,7 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
     queries with routing of the certified band to Barnes-Hut.  Compared with
     Barnes-Hut alone on the same queries."""
     from paper_2108_10480_amd import surrogate as S
-    alpha, beta, band = args.alpha, args.beta, 0.05
+    alpha, beta, band = ICO_ALPHAS[0], args.beta, 0.05
     ev = lambda: torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     Xtr = torch.as_tensor(scenes.surrogate_samples(sc, args.sur_train, seed=6), device="cuda")

@@ -69,6 +69,7 @@ enum {
                                        are all below exp(-64) of the running maximum (by default
                                        those are skipped when alpha x scene diagonal > 1000:
                                        they cannot change an FP32 result)                      */
+#define SD_COUNTERS_BY_CLASS 0x20u  /* sd_eval_counters: exact leaf terms per primitive class   */
 
 typedef struct sd_params {
     float alpha;     /* accuracy / smoothness, > 0 (Eq. 3)                                   */
@@ -177,7 +178,9 @@ int sd_eval_brute(const sd_scene *scene, const float *Q, int64_t nQ, const sd_pa
                   float *d_out, float *grad_out, void *stream);
 
 /* Per-query work counters of the Barnes-Hut traversal: counts_out nQ x 3 int32
- * = (nodes visited, far-field terms, exact leaf terms). */
+ * = (nodes visited, far-field terms, exact leaf terms); with
+ * SD_COUNTERS_BY_CLASS in params->flags, nQ x 5 = (nodes visited, far-field
+ * terms, exact point, edge and triangle leaf terms). */
 int sd_eval_counters(const sd_scene *scene, const float *Q, int64_t nQ, const sd_params *params,
                      int32_t *counts_out, void *stream);
 

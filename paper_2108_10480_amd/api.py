@@ -23,6 +23,7 @@ SD_ROOTLOG_F64 = 0x2
 SD_NO_QUERY_SORT = 0x4
 SD_NO_CONSERVATIVE_ROUNDING = 0x8
 SD_NO_PRUNE = 0x10
+SD_COUNTERS_BY_CLASS = 0x20
 
 _c_p = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -221,9 +222,11 @@ def sd_eval_brute(scene, Q, alpha, alpha_u=0.0, flags=0, grad=True):
 
 
 def sd_eval_counters(scene, Q, alpha, beta=0.5, alpha_u=0.0, flags=0):
-    """Per-query (nodes visited, far-field terms, exact leaves)."""
+    """Per-query (nodes visited, far-field terms, exact leaves); with
+    SD_COUNTERS_BY_CLASS the leaves split into points, edges, triangles."""
     Qp, n = _queries(Q)
-    c = torch.empty((n, 3), dtype=torch.int32, device=Q.device)
+    k = 5 if flags & SD_COUNTERS_BY_CLASS else 3
+    c = torch.empty((n, k), dtype=torch.int32, device=Q.device)
     p = params(alpha, beta, alpha_u, flags)
     _check(lib().sd_eval_counters(scene.handle, Qp, _i64(n), ctypes.byref(p), _c_p(c.data_ptr()),
                                   _stream()))

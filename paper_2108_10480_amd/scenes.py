@@ -350,11 +350,17 @@ def rigid_transforms(K, seed=5, lo=(5.0, -8.0, 0.2), hi=(95.0, 8.0, 6.0)):
 # --------------------------------------------------------------------------
 # terrain + mesh scene for the alpha / precision sweep
 # --------------------------------------------------------------------------
-def _gradient_noise_2d(x, y, rng, period=256):
-    """Seeded 2D gradient (Perlin-style) noise: random unit gradients on an
-    integer lattice, quintic fade, bilinear blend of the corner dot products."""
+def _gradient_table(rng, period=256):
+    """Random unit gradients on a period x period integer lattice."""
     ang = rng.uniform(0, 2 * np.pi, (period, period))
-    gx, gy = np.cos(ang), np.sin(ang)
+    return np.cos(ang), np.sin(ang)
+
+
+def _gradient_noise_2d(x, y, table):
+    """Seeded 2D gradient (Perlin-style) noise: the lattice gradients of
+    `table`, quintic fade, bilinear blend of the corner dot products."""
+    gx, gy = table
+    period = gx.shape[0]
     xi, yi = np.floor(x).astype(np.int64), np.floor(y).astype(np.int64)
     fx, fy = x - xi, y - yi
     fade = lambda t: t * t * t * (t * (6 * t - 15) + 10)
@@ -369,6 +375,28 @@ def _gradient_noise_2d(x, y, rng, period=256):
     return out
 
 
+def _terrain_heights(x, y, tables, chunk=1 << 20):
+    """z = 0.25 sum_{o<6} 0.5^o n(2^o 2 (x, y)), elementwise, in chunks on a
+    thread pool (numpy releases the interpreter lock in its array loops; the
+    per-element arithmetic does not depend on the chunking)."""
+    import concurrent.futures as cf
+    import os
+    z = np.zeros(len(x))
+
+    def work(lo):
+        hi = min(lo + chunk, len(x))
+        xs, ys = x[lo:hi], y[lo:hi]
+        acc = np.zeros(hi - lo)
+        for o in range(6):
+            f = 2.0 ** o * 2.0
+            acc += 0.25 * 0.5 ** o * _gradient_noise_2d(f * xs + 37.0, f * ys + 91.0, tables[o])
+        z[lo:hi] = acc
+
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(work, range(0, len(x), chunk)))
+    return z
+
+
 def terrain_scene(scale=1.0, seed=9):
     """Heightfield point cloud over [-1, 1]^2 (z = 0.25 sum_{o<6} 0.5^o
     n(2^o 2 (x, y)) with seeded gradient noise n, plus N(0, 0.005^2)), a torus
@@ -379,11 +407,9 @@ def terrain_scene(scale=1.0, seed=9):
     rng = np.random.default_rng(seed)
     n = max(int(round(20_000_000 * scale)), 100)
     x, y = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
-    z = np.zeros(n)
     noise_rng = np.random.default_rng(seed + 1000)
-    for o in range(6):
-        f = 2.0 ** o * 2.0
-        z += 0.25 * 0.5 ** o * _gradient_noise_2d(f * x + 37.0, f * y + 91.0, noise_rng)
+    tables = [_gradient_table(noise_rng) for _ in range(6)]
+    z = _terrain_heights(x, y, tables)
     z += rng.normal(0, 0.005, n)
     pts = np.stack([x, y, z], 1)
     k = np.sqrt(scale)
