@@ -733,9 +733,12 @@ def rigid_leg(args, np, torch, api, scenes):
         lo, hi = scenes.scene_aabb(sc)
         floor = 1e-3 * float(np.linalg.norm(hi - lo))
         dg = d[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+        gg = g[torch.as_tensor(idx, device="cuda")].cpu().numpy()
         err = O.value_error(dg, dr, floor)
+        dm = O.dmin_tree(osc, trees, Qs)
         res["parity_sample"] = {"n": len(dg), "max_err_vs_oracle": float(err.max()),
-                                "conservative_violations": int(np.sum(dg > dr)),
+                                "max_grad_err_vs_oracle": float(O.grad_error(gg, gr).max()),
+                                "conservative_violations": int(np.sum(dg.astype(np.float64) > dm)),
                                 "oracle_queries_per_s": len(idx) / dt}
         # query-mesh distance of two whole placements against the oracle composite
         from oracle import qmesh as QM
