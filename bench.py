@@ -517,8 +517,8 @@ def prims_leg(args, np, torch, api, scenes, sc, scene):
 def contact_leg(args, np, torch, api, scenes):
     """Frictionless rigid-body contact (Sec. 4.5): the street body (a torus)
     dropped onto the street scene at scale 0.1;
-    implicit steps of 10 ms, each a primal-dual interior-point solve of one
-    smooth-distance constraint (value and gradient on the GPU)."""
+    implicit steps of 10 ms, each a sequential-quadratic-programming solve of
+    one smooth-distance constraint (value and gradient on the GPU)."""
     from paper_2108_10480_amd import contact as C
     sc, body_v = scenes.street_scene(0.1)
     scene = api.upload_scene(sc)
@@ -542,11 +542,13 @@ def contact_leg(args, np, torch, api, scenes):
     dt = time.perf_counter() - t0
     evals = step.evals - evals0
     return {"workload": f"street scene at scale 0.1 ({sc.counts()[0]} points, {sc.counts()[1]} wire segments, "
-                        f"{sc.counts()[2]} triangles); body of {len(body_v)} vertices dropped from 1 m, "
+                        f"{sc.counts()[2]} triangles); body of {len(body_v)} vertices dropped, "
                         f"alpha=alpha_q=50, d_safe=0.05, h=0.01, {nsteps} steps from 0.3 m above the scene under it",
-            "ms_per_step": dt / nsteps * 1e3, "ipm_iterations_mean": float(np.mean(iters)),
-            "solves_ended_without_feasible_step": step.stalls,
-            "constraint_evaluations": evals, "ms_per_evaluation": dt / evals * 1e3,
+            "ms_per_step": dt / nsteps * 1e3, "sqp_iterations_mean": float(np.mean(iters)),
+            "sqp_iterations_max": int(np.max(iters)), "solves_not_converged": step.stalls,
+            "solves_ended_infeasible": step.infeasible, "constraint_target_c_res": step.c_res,
+            "constraint_evaluations": evals, "exact_evaluations_near_contact": step.exact_evals,
+            "exact_band": step.exact_band, "ms_per_evaluation": dt / evals * 1e3,
             "start_height_above_ground": float(start[2] - ground), "final_height_above_ground": float(body.p[2] - ground),
             "final_speed": float(np.linalg.norm(body.v))}
 

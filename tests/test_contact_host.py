@@ -28,18 +28,19 @@ def test_left_jacobian_by_finite_differences():
             np.testing.assert_allclose(axial / h, J[:, k], atol=1e-6)
 
 
-def _plane_step(jump=0.0, h0=0.0):
+def _plane_step(jump=0.0, h0=0.0, width=1e-5):
     """A ContactStep whose constraint is a stand-in: the height of the body's
     centre above the plane z = h0, minus d_safe, with an optional downward
-    jump of `jump` within 1e-6 of the boundary (the kind of rounding-sized
-    discontinuity the Barnes-Hut constraint has there)."""
+    jump of `jump` within `width` of the boundary (the kind of small
+    discontinuity the Barnes-Hut constraint has there), where the returned
+    gradient is zero (no model of the constraint there predicts the jump)."""
     step = C.ContactStep(scene=None, alpha=50.0, alpha_q=50.0, d_safe=0.05, h=0.01)
 
     def constraint(body, x, R0, grad=True):
         step.evals += 1
         c = x[2] - h0 - step.d_safe
-        if 0.0 < c < 1e-6:
-            c -= jump
+        if jump > 0.0 and 0.0 < c < width:
+            return c - jump, np.zeros(6)
         return c, np.array([0.0, 0.0, 1.0, 0.0, 0.0, 0.0])
 
     step.constraint = constraint
@@ -65,12 +66,13 @@ def test_falling_body_rests_on_a_smooth_constraint():
 
 
 def test_jump_next_to_the_boundary_ends_at_a_feasible_iterate():
-    """When no step along the Newton direction stays feasible, the solve
-    stops at its last iterate (feasible) instead of failing."""
-    step = _plane_step(jump=1e-5)
+    """When the solve ends at an infeasible point (here: the target c_res
+    lies inside a jump that takes the constraint below zero), the step
+    returns its feasible start instead, and the solve is counted."""
+    step = _plane_step(jump=2e-5)
     body = C.RigidBody(_cube(), mass=1.0, p=(0.0, 0.0, 0.3))
     for _ in range(80):
         it, c = step.step(body)
-        assert c > 0
+        assert c > 0 and step.c_res < 1e-5
         assert body.p[2] - 0.05 > 0.0
     assert step.stalls > 0
