@@ -822,6 +822,7 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
         ms = timed(sur_path)
         _, _, _, nfb = S.sd_eval_surrogate(scene, sur, Xin, alpha, beta, band=band, out=d, grad_out=g,
                                            routed=routed)
+        nfb = int(nfb)
         torch.cuda.synchronize()
         keep = routed == 0
         e_out = (d - de).abs()[keep]

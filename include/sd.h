@@ -227,6 +227,18 @@ int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64_t K,
                      float *Rbar, float *tbar, float *Xbar, void *stream);
 
 /*
+ * The same adjoint for the query-mesh distances D_k of the K rigidly moved
+ * copies of the m points (Sec. 3.6, Eq. 6-8, with the rigid degrees of freedom
+ * of Sec. 4.5): gbar_kj = w_kj * Dbar_k is formed inside the kernels from
+ * w = dD_k/dd_kj (K x m, the weights of sd_query_mesh_lse) and the upstream
+ * Dbar = dL/dD_k (K), all device memory.  Same outputs, layout and
+ * determinism as sd_rigid_adjoint; SD_EINVAL for a null Dbar when K > 0.
+ */
+int sd_rigid_qmesh_adjoint(const float *X, int64_t m, const float *R, int64_t K, const float *w,
+                           const float *Dbar, const float *grad, float *Rbar, float *tbar, float *Xbar,
+                           void *stream);
+
+/*
  * Value and gradient for query primitives that are edges or triangles
  * (Sec. 3.4): G is n x nv x 3 (nv = 2: edges, 3: triangles; 1: points, the
  * same as sd_eval_grad), device memory.  d(f_i, g) is the simplex-simplex
@@ -395,12 +407,30 @@ int sd_surrogate_load(sd_surrogate *sur, const float *theta_host, const float *m
  * sd_surrogate_certify_cells, band + the margin of the query's cell) are then
  * evaluated exactly (sd_eval_grad semantics with `params`, in Morton order
  * unless SD_NO_QUERY_SORT) and overwritten.  routed (nQ bytes, may be
- * NULL) receives 1 for those queries.  *n_fallback_host (may be NULL) receives
- * their number.  The surrogate must have been trained for this scene and
- * params.  Synchronises `stream` once (to size the exact pass). */
+ * NULL) receives 1 for those queries.  *n_fallback (device, one uint32; may
+ * be NULL) receives their number.  The surrogate must have been trained for
+ * this scene and params.  Asynchronous: the number of routed queries stays on
+ * the device, where the compaction, the Morton order and the exact pass read
+ * it (their launches are sized for nQ; waves beyond the count exit at once),
+ * so the call never waits for the GPU. */
 int sd_eval_surrogate(const sd_scene *scene, const sd_surrogate *sur, const float *Q, int64_t nQ,
                       const sd_params *params, float band, float *d_out, float *grad_out,
-                      uint8_t *routed, int64_t *n_fallback_host, void *stream);
+                      uint8_t *routed, uint32_t *n_fallback, void *stream);
+
+/* Device memory budget of the library (all devices together; default: none).
+ * Every device allocation of the library (scene hierarchies, surrogate state,
+ * the stream-ordered scratch of a call) that would take the bytes it holds
+ * above `bytes` fails with SD_ENOMEM, as a failed device allocation does; the
+ * call that made it releases everything it had taken and returns SD_ENOMEM.
+ * bytes < 0 removes the budget.  The static array of sd_eval_grad_noalloc is
+ * not counted.  Callers: services that share a GPU and must bound the
+ * library's footprint, and tests of the out-of-memory paths. */
+int sd_set_memory_budget(int64_t bytes);
+
+/* Device bytes the library holds now: scenes, surrogates, and the scratch of
+ * calls whose release has not been enqueued yet (scratch is returned to the
+ * stream's pool in stream order when its call returns). */
+int sd_memory_in_use(int64_t *bytes_out);
 
 /* Message of the last failed call on this thread (thread-local storage owned
  * by the library; valid until the next failing call on the thread). */

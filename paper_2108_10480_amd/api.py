@@ -3,7 +3,8 @@ the computation runs in the HIP kernels behind the C ABI (include/sd.h).
 
 PyTorch supplies device memory and the current HIP stream.  Functions keep the
 C names: sd_build_bvh, sd_eval, sd_eval_grad, sd_eval_brute, sd_eval_counters,
-sd_export_bvh, sd_export_weights, sd_rigid_transform, sd_rigid_adjoint, plus
+sd_export_bvh, sd_export_weights, sd_rigid_transform, sd_rigid_adjoint,
+sd_rigid_qmesh_adjoint, sd_query_mesh_lse, sd_eval_grad_prims, sd_sphere_trace, plus
 the surrogate entry points in ``surrogate.py``.
 """
 from __future__ import annotations
@@ -52,11 +53,11 @@ _lib = None
 EXPORTED = ["sd_build_bvh", "sd_free_scene", "sd_scene_info_get", "sd_eval", "sd_eval_grad",
             "sd_eval_brute", "sd_eval_counters", "sd_export_bvh", "sd_export_weights",
             "sd_query_order", "sd_eval_grad_ordered", "sd_eval_grad_noalloc",
-            "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint", "sd_query_mesh_lse", "sd_sphere_trace", "sd_eval_grad_prims",
+            "sd_triangle_weight_basis", "sd_rigid_transform", "sd_rigid_adjoint", "sd_rigid_qmesh_adjoint", "sd_query_mesh_lse", "sd_sphere_trace", "sd_eval_grad_prims",
             "sd_surrogate_create", "sd_surrogate_free", "sd_surrogate_forward",
             "sd_surrogate_loss_grad", "sd_surrogate_adam", "sd_surrogate_train_step",
             "sd_surrogate_certify", "sd_surrogate_certify_cells", "sd_surrogate_save", "sd_surrogate_load", "sd_eval_surrogate",
-            "sd_last_error"]
+            "sd_set_memory_budget", "sd_memory_in_use", "sd_last_error"]
 
 
 def lib():
@@ -144,6 +145,18 @@ def sd_build_bvh(V, P=None, E=None, T=None, flags=0, all_points=False):
     _check(lib().sd_build_bvh(Vp, _i64(nV), Pp, _i64(nP), Ep, _i64(nE), Tp, _i64(nT),
                               ctypes.c_uint32(flags), _stream(), ctypes.byref(h)))
     return Scene(h)
+
+
+def sd_set_memory_budget(nbytes):
+    """Budget of the library's device memory in bytes (None or < 0: none)."""
+    _check(lib().sd_set_memory_budget(_i64(-1 if nbytes is None else int(nbytes))))
+
+
+def sd_memory_in_use():
+    """Device bytes the library holds now."""
+    out = ctypes.c_int64()
+    _check(lib().sd_memory_in_use(ctypes.byref(out)))
+    return out.value
 
 
 def params(alpha, beta=0.5, alpha_u=0.0, flags=0):
@@ -289,6 +302,26 @@ def sd_rigid_adjoint(X, R, gbar, grad, want_x=True):
     return Rbar.reshape(K, 3, 3), tbar, Xbar
 
 
+def sd_rigid_qmesh_adjoint(X, R, w, Dbar, grad, want_x=True):
+    """sd_rigid_adjoint with gbar_kj = w_kj Dbar_k formed in the kernels."""
+    Xp, m = _dptr(X, torch.float32, "X", 3)
+    Rf = R.reshape(-1, 9).contiguous()
+    Rp, K = _dptr(Rf, torch.float32, "R", 9)
+    wc = w.reshape(-1).contiguous()
+    Db = Dbar.reshape(-1).contiguous()
+    _dptr(Db.reshape(-1, 1), torch.float32, "Dbar", 1)
+    gd = grad.reshape(-1, 3).contiguous()
+    if wc.numel() != K * m or gd.shape[0] != K * m or Db.numel() != K:
+        raise ValueError("w / grad must have K*m entries and Dbar K")
+    Rbar = torch.empty((K, 9), dtype=torch.float32, device=X.device)
+    tbar = torch.empty((K, 3), dtype=torch.float32, device=X.device)
+    Xbar = torch.empty((m, 3), dtype=torch.float32, device=X.device) if want_x else None
+    _check(lib().sd_rigid_qmesh_adjoint(Xp, _i64(m), Rp, _i64(K), _c_p(wc.data_ptr()), _c_p(Db.data_ptr()),
+                                        _c_p(gd.data_ptr()), _c_p(Rbar.data_ptr()), _c_p(tbar.data_ptr()),
+                                        _c_p(Xbar.data_ptr() if Xbar is not None else 0), _stream()))
+    return Rbar.reshape(K, 3, 3), tbar, Xbar
+
+
 class RigidSmoothDistance(torch.autograd.Function):
     """d_kj = smooth distance of R_k x_j + t_k, differentiable in (R, t, X) by the
     hand-written adjoint (sd_rigid_adjoint), the forward gradient from
@@ -390,7 +423,7 @@ class RigidQueryMeshDistance(torch.autograd.Function):
     """D_k = smooth distance between the data mesh and the point query mesh
     {R_k x_j + t_k} (Eq. 6 with alpha_q), differentiable in (R, t, X): the
     upstream dL/dD_k times the weights w_kj = dD_k/dd_kj feeds the rigid
-    adjoint (sd_rigid_adjoint)."""
+    adjoint (sd_rigid_qmesh_adjoint forms that product on the GPU)."""
 
     @staticmethod
     def forward(ctx, X, R, t, scene, alpha, beta, alpha_u, flags, alpha_q):
@@ -405,8 +438,7 @@ class RigidQueryMeshDistance(torch.autograd.Function):
     @staticmethod
     def backward(ctx, Dbar):
         X, R, g, w = ctx.saved_tensors
-        gbar = (w * Dbar.reshape(-1, 1)).contiguous()
-        Rbar, tbar, Xbar = sd_rigid_adjoint(X, R, gbar, g, want_x=ctx.needs_input_grad[0])
+        Rbar, tbar, Xbar = sd_rigid_qmesh_adjoint(X, R, w, Dbar, g, want_x=ctx.needs_input_grad[0])
         return (Xbar, Rbar.reshape(R.shape), tbar, None, None, None, None, None, None)
 
 

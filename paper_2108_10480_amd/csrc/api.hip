@@ -2,7 +2,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "sd_internal.h"
@@ -16,6 +18,84 @@ void set_error(const std::string &msg) { g_err = msg; }
 int fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory accounting: the bytes of every live allocation, their sum and
+// the budget, under one lock (allocations are few per call).
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_mem_mu;
+std::unordered_map<void *, size_t> g_mem_live;
+int64_t g_mem_in_use = 0;
+int64_t g_mem_budget = -1;   // < 0: none
+
+int mem_admit(size_t bytes, const char *what) {
+    if (g_mem_budget >= 0 && g_mem_in_use + (int64_t)bytes > g_mem_budget)
+        return fail(SD_ENOMEM, std::string(what) + ": " + std::to_string(bytes) +
+                                   " bytes would exceed the device memory budget of " +
+                                   std::to_string(g_mem_budget) + " bytes (" + std::to_string(g_mem_in_use) +
+                                   " in use)");
+    return SD_OK;
+}
+
+int mem_failed(hipError_t e, size_t bytes, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? SD_ENOMEM : SD_EHIP,
+                std::string(what) + ": device allocation of " + std::to_string(bytes) + " bytes: " +
+                    hipGetErrorString(e));
+}
+
+void mem_record(void *p, size_t bytes) {
+    g_mem_live[p] = bytes;
+    g_mem_in_use += (int64_t)bytes;
+}
+
+void mem_forget(void *p) {
+    auto it = g_mem_live.find(p);
+    if (it == g_mem_live.end()) return;
+    g_mem_in_use -= (int64_t)it->second;
+    g_mem_live.erase(it);
+}
+}  // namespace
+
+int dev_malloc(void **p, size_t bytes, const char *what) {
+    *p = nullptr;
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    SD_TRY(mem_admit(bytes, what));
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return mem_failed(e, bytes, what);
+    }
+    mem_record(*p, bytes);
+    return SD_OK;
+}
+
+int dev_malloc_async(void **p, size_t bytes, hipStream_t s, const char *what) {
+    *p = nullptr;
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    SD_TRY(mem_admit(bytes, what));
+    hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return mem_failed(e, bytes, what);
+    }
+    mem_record(*p, bytes);
+    return SD_OK;
+}
+
+void dev_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    mem_forget(p);
+    (void)hipFree(p);
+}
+
+void dev_free_async(void *p, hipStream_t s) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    mem_forget(p);
+    (void)hipFreeAsync(p, s);
 }
 
 int build_scene(sd_scene *sc, const float *V, int64_t nV, const int32_t *P, int64_t nP,
@@ -46,6 +126,19 @@ static int check_eval(const sd_scene *sc, const float *Q, int64_t nq, const sd_p
 extern "C" {
 
 const char *sd_last_error(void) { return sd::g_err.c_str(); }
+
+int sd_set_memory_budget(int64_t bytes) {
+    std::lock_guard<std::mutex> lock(sd::g_mem_mu);
+    sd::g_mem_budget = bytes < 0 ? -1 : bytes;
+    return SD_OK;
+}
+
+int sd_memory_in_use(int64_t *bytes_out) {
+    if (!bytes_out) return sd::fail(SD_EINVAL, "sd_memory_in_use: null output");
+    std::lock_guard<std::mutex> lock(sd::g_mem_mu);
+    *bytes_out = sd::g_mem_in_use;
+    return SD_OK;
+}
 
 int sd_build_bvh(const float *V, int64_t nV, const int32_t *P, int64_t nP, const int32_t *E,
                  int64_t nE, const int32_t *T, int64_t nT, uint32_t flags, void *stream,
@@ -85,9 +178,9 @@ int sd_free_scene(sd_scene *sc) {
         // hi[c] points into the interleaved lo[c] allocation
         for (void *p : {(void *)sc->lo[c], (void *)sc->leaf[c], (void *)sc->prim_id[c],
                         (void *)sc->wt[c]})
-            if (p) (void)hipFree(p);
+            sd::dev_free(p);
     }
-    if (sc->tri_table) (void)hipFree(sc->tri_table);
+    sd::dev_free(sc->tri_table);
     delete sc;
     return SD_OK;
 }

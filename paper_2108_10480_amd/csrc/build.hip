@@ -428,10 +428,7 @@ k_tri_class(const float *__restrict__ wt, int64_t nT, const int32_t *__restrict_
 template <typename T>
 int dalloc(T **p, int64_t count, hipStream_t s, int64_t *acc = nullptr) {
     size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMallocAsync((void **)p, bytes, s);
-    if (e != hipSuccess)
-        return fail(e == hipErrorOutOfMemory ? SD_ENOMEM : SD_EHIP,
-                    std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    SD_TRY(dev_malloc_async((void **)p, bytes, s, "sd_build_bvh"));
     if (acc) *acc += (int64_t)bytes;
     return SD_OK;
 }

@@ -1135,7 +1135,7 @@ template <bool GRAD, bool COUNT, int MASK>
 __global__ void __launch_bounds__(kB) SD_EVAL_ATTR
 k_eval(EvalArgs A) {
     int i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
-    if (i >= A.nthr) return;
+    if (i >= (A.nthr_dev ? min(A.nthr, (int)min(*A.nthr_dev, 0x7fffffffu)) : A.nthr)) return;
     int qi = A.perm ? (int)A.perm[i] : i;
     if ((unsigned)qi >= (unsigned)A.nq) return;
     float qx = A.Q[3 * (int64_t)qi], qy = A.Q[3 * (int64_t)qi + 1], qz = A.Q[3 * (int64_t)qi + 2];
@@ -1216,10 +1216,11 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 }
 
 __global__ void __launch_bounds__(kB)
-k_query_keys(const float *__restrict__ Q, const uint32_t *__restrict__ idx, int64_t n, float lx,
-             float ly, float lz, float sx, float sy, float sz, uint64_t *__restrict__ keys,
-             uint32_t *__restrict__ vals) {
+k_query_keys(const float *__restrict__ Q, const uint32_t *__restrict__ idx, int64_t n,
+             const uint32_t *__restrict__ n_dev, float lx, float ly, float lz, float sx, float sy,
+             float sz, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (n_dev) n = min(n, (int64_t)*n_dev);
     if (i >= n) return;
     int64_t j = idx ? (int64_t)idx[i] : i;
     float u[3] = {(Q[3 * j] - lx) * sx, (Q[3 * j + 1] - ly) * sy, (Q[3 * j + 2] - lz) * sz};
@@ -1381,9 +1382,9 @@ size_t query_order_scratch_bytes(int64_t nq) {
 // every side (queries outside clamp to the boundary cells), with the scratch
 // given by the caller (query_order_scratch_bytes(nq) bytes, 256-aligned).
 // With idx, only the n queries idx[0..n) are ordered and perm receives those
-// indices sorted.
+// indices sorted; with n_dev as well, only idx[0..min(n, *n_dev)).
 int query_order_into(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, void *scratch,
-                     hipStream_t s, const uint32_t *idx) {
+                     hipStream_t s, const uint32_t *idx, const uint32_t *n_dev = nullptr) {
     if (nq <= 0) return SD_OK;
     char *p = static_cast<char *>(scratch);
     const size_t n = (size_t)nq;
@@ -1400,20 +1401,20 @@ int query_order_into(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *p
         ext[a] = 2.f * e;
     }
     unsigned grid = (unsigned)((nq + kB - 1) / kB);
-    hipLaunchKernelGGL(k_query_keys, dim3(grid), dim3(kB), 0, s, Q, idx, nq, lo[0], lo[1], lo[2],
+    hipLaunchKernelGGL(k_query_keys, dim3(grid), dim3(kB), 0, s, Q, idx, nq, n_dev, lo[0], lo[1], lo[2],
                        1.f / ext[0], 1.f / ext[1], 1.f / ext[2], keys, perm);
-    SD_TRY(radix_sort_pairs(keys, perm, keys2, vals2, nq, 30, p, s));
+    SD_TRY(radix_sort_pairs(keys, perm, keys2, vals2, nq, 30, p, s, n_dev));
     return SD_OK;
 }
 
 // query_order_into with stream-ordered scratch of its own
 int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s,
-                const uint32_t *idx) {
+                const uint32_t *idx, const uint32_t *n_dev) {
     if (nq <= 0) return SD_OK;
     char *scratch;
     AsyncScratch tmp(s);
     SD_TRY(tmp.alloc(&scratch, (int64_t)query_order_scratch_bytes(nq)));
-    return query_order_into(sc, Q, nq, perm, scratch, s, idx);
+    return query_order_into(sc, Q, nq, perm, scratch, s, idx, n_dev);
 }
 
 // ---------------------------------------------------------------------------
@@ -1536,16 +1537,19 @@ static int make_args(const sd_scene *sc, const sd_params *p, EvalArgs &A) {
 
 int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, int64_t nq,
                   const sd_params *p, float *d_out, float *g_out, int32_t *counts, bool brute,
-                  hipStream_t s, int64_t nthr) {
+                  hipStream_t s, int64_t nthr, const uint32_t *nthr_dev) {
     if (nthr < 0) nthr = nq;
     if (nq == 0 || nthr == 0) return SD_OK;
     if (nq > (int64_t)0x7fffffff - kB) return fail(SD_EUNSUPPORTED, "more than 2^31 queries per call");
     if (nthr != nq && (!perm_in || brute || counts || nthr > nq))
         return fail(SD_EINVAL, "a thread count below the query count needs an index list");
+    if (nthr_dev && (!perm_in || brute || counts))
+        return fail(SD_EINVAL, "a thread count on the device needs an index list");
     EvalArgs A;
     int mask = make_args(sc, p, A);
     A.nq = (int32_t)nq;
     A.nthr = (int32_t)nthr;
+    A.nthr_dev = nthr_dev;
     A.Q = Q;
     A.d_out = d_out;
     A.g_out = g_out;

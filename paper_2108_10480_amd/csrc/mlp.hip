@@ -710,6 +710,13 @@ __global__ void k_compact(const uint8_t *__restrict__ f, const uint32_t *__restr
     if (i < n && f[i]) idx[pos[i]] = (uint32_t)i;
 }
 
+// number of flagged entries: the exclusive prefix sum at the last entry plus
+// its flag (one thread)
+__global__ void k_flag_count(const uint8_t *__restrict__ f, const uint32_t *__restrict__ pos, int64_t n,
+                             uint32_t *__restrict__ count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) count[0] = n > 0 ? pos[n - 1] + (f[n - 1] ? 1u : 0u) : 0u;
+}
+
 // per-cell maximum of the sample errors (non-negative floats order like their
 // bit patterns; -1 marks an empty cell)
 __global__ void k_cell_max(const float *__restrict__ X, const float *__restrict__ err, int64_t n,
@@ -782,12 +789,7 @@ constexpr int kSplitRows = 2048;   // split-K length of the weight-gradient prod
 constexpr int kSumRows = 256;      // rows per partial of the column sums (bias gradients)
 
 int sur_alloc(sd_surrogate *h, void **p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return fail(SD_ENOMEM, "surrogate: device allocation of " + std::to_string(bytes) +
-                                   " bytes failed");
-    }
+    SD_TRY(dev_malloc(p, bytes, "surrogate"));
     h->owned.push_back(*p);
     return SD_OK;
 }
@@ -934,8 +936,13 @@ extern "C" int sd_surrogate_create(const float *B_host, const float *theta_host,
     if (max_batch < 0 || max_batch % 64 != 0 || max_batch > (1 << 24))
         return fail(SD_EINVAL, "sd_surrogate_create: max_batch must be a multiple of 64 in [0, 2^24]");
     hipStream_t s = (hipStream_t)stream;
-    auto *h = new sd_surrogate();
-    SD_HIP(hipGetDevice(&h->device));
+    auto *h = new (std::nothrow) sd_surrogate();
+    if (!h) return fail(SD_ENOMEM, "sd_surrogate_create: host allocation");
+    hipError_t de = hipGetDevice(&h->device);
+    if (de != hipSuccess) {
+        delete h;
+        return fail(SD_EHIP, std::string("sd_surrogate_create: hipGetDevice: ") + hipGetErrorString(de));
+    }
     h->max_batch = max_batch;
     auto fl = [&](float **p, size_t n) { return sur_alloc(h, (void **)p, n * sizeof(float)); };
     auto bf = [&](__bf16 **p, size_t n) { return sur_alloc(h, (void **)p, n * sizeof(__bf16)); };
@@ -978,7 +985,7 @@ extern "C" int sd_surrogate_create(const float *B_host, const float *theta_host,
     }
     if (!rc) rc = pack(h, s);
     if (rc) {
-        for (void *p : h->owned) (void)hipFree(p);
+        for (void *p : h->owned) dev_free(p);
         delete h;
         return rc;
     }
@@ -988,8 +995,8 @@ extern "C" int sd_surrogate_create(const float *B_host, const float *theta_host,
 
 extern "C" int sd_surrogate_free(sd_surrogate *h) {
     if (!h) return SD_OK;
-    if (h->cell_eps) (void)hipFree(h->cell_eps);
-    for (void *p : h->owned) (void)hipFree(p);
+    dev_free(h->cell_eps);
+    for (void *p : h->owned) dev_free(p);
     delete h;
     return SD_OK;
 }
@@ -1077,11 +1084,12 @@ extern "C" int sd_surrogate_certify_cells(sd_surrogate *h, const float *X, const
     hipStream_t s = (hipStream_t)stream;
     const int64_t nc = (int64_t)grid * grid * grid;
     if (h->cell_eps && h->cell_cap < nc) {
-        SD_HIP(hipFree(h->cell_eps));
+        dev_free(h->cell_eps);
         h->cell_eps = nullptr;
+        h->cell_cap = 0;
     }
     if (!h->cell_eps) {
-        SD_HIP(hipMalloc((void **)&h->cell_eps, nc * sizeof(float)));
+        SD_TRY(dev_malloc((void **)&h->cell_eps, nc * sizeof(float), "sd_surrogate_certify_cells"));
         h->cell_cap = nc;
     }
     MlpArgs A = {};
@@ -1138,7 +1146,7 @@ extern "C" int sd_surrogate_load(sd_surrogate *h, const float *theta_host, const
 
 extern "C" int sd_eval_surrogate(const sd_scene *sc, const sd_surrogate *h, const float *Q, int64_t nQ,
                                  const sd_params *p, float band, float *d_out, float *grad_out,
-                                 uint8_t *routed, int64_t *n_fallback_host, void *stream) {
+                                 uint8_t *routed, uint32_t *n_fallback, void *stream) {
     if (!sc || !h || !p) return fail(SD_EINVAL, "sd_eval_surrogate: null argument");
     if (nQ < 0) return fail(SD_EINVAL, "sd_eval_surrogate: nQ < 0");
     if (!(band >= 0.f)) return fail(SD_EINVAL, "sd_eval_surrogate: band must be >= 0");
@@ -1146,15 +1154,21 @@ extern "C" int sd_eval_surrogate(const sd_scene *sc, const sd_surrogate *h, cons
         return fail(SD_EINVAL, "sd_eval_surrogate: bad parameters");
     if (sc->n[0] + sc->n[1] + sc->n[2] == 0) return fail(SD_EINVAL, "sd_eval_surrogate: empty scene");
     if (nQ > 0x7fffffffll - 256) return fail(SD_EUNSUPPORTED, "sd_eval_surrogate: more than 2^31 queries");
-    if (n_fallback_host) *n_fallback_host = 0;
-    if (nQ == 0) return SD_OK;
-    if (!Q || !d_out || !grad_out) return fail(SD_EINVAL, "sd_eval_surrogate: null array");
     hipStream_t s = (hipStream_t)stream;
+    if (nQ == 0) {
+        if (n_fallback) {
+            hipLaunchKernelGGL(k_flag_count, dim3(1), dim3(64), 0, s, nullptr, nullptr, (int64_t)0, n_fallback);
+            SD_HIP(hipGetLastError());
+        }
+        return SD_OK;
+    }
+    if (!Q || !d_out || !grad_out) return fail(SD_EINVAL, "sd_eval_surrogate: null array");
     uint8_t *flag = routed;
-    uint32_t *f32 = nullptr, *pos = nullptr, *idx = nullptr, *ord = nullptr;
+    uint32_t *f32 = nullptr, *pos = nullptr, *idx = nullptr, *ord = nullptr, *nfb = n_fallback;
     char *temp = nullptr;
     AsyncScratch tmp(s);
     if (!flag) SD_TRY(tmp.alloc(&flag, nQ));
+    if (!nfb) SD_TRY(tmp.alloc(&nfb, 1));
     SD_TRY(launch_mlp(h, Q, nQ, d_out, grad_out, flag, band + h->eps_cert, nullptr, nullptr, s, band));
     // compaction of the routed queries (in index order), then Morton order
     SD_TRY(tmp.alloc(&f32, nQ));
@@ -1162,25 +1176,19 @@ extern "C" int sd_eval_surrogate(const sd_scene *sc, const sd_surrogate *h, cons
     SD_TRY(tmp.alloc(&temp, (int64_t)radix_sort_temp_bytes(nQ)));
     hipLaunchKernelGGL(k_flags_u32, dim3(blocks(nQ)), dim3(256), 0, s, flag, nQ, f32);
     SD_TRY(exclusive_scan_u32(f32, pos, nQ, temp, s));
-    uint32_t last_pos = 0;
-    uint8_t last_flag = 0;
-    SD_HIP(hipMemcpyAsync(&last_pos, pos + nQ - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    SD_HIP(hipMemcpyAsync(&last_flag, flag + nQ - 1, 1, hipMemcpyDeviceToHost, s));
-    SD_HIP(hipStreamSynchronize(s));
-    const int64_t nfb = (int64_t)last_pos + last_flag;
+    // the count of routed queries stays on the device: the compaction, the
+    // Morton order and the exact pass are launched for all nQ and read it
+    hipLaunchKernelGGL(k_flag_count, dim3(1), dim3(64), 0, s, flag, pos, nQ, nfb);
+    SD_TRY(tmp.alloc(&idx, nQ));
+    hipLaunchKernelGGL(k_compact, dim3(blocks(nQ)), dim3(256), 0, s, flag, pos, nQ, idx);
+    SD_HIP(hipGetLastError());
+    const uint32_t *perm = idx;
     int rc = SD_OK;
-    if (nfb > 0) {
-        SD_TRY(tmp.alloc(&idx, nfb));
-        hipLaunchKernelGGL(k_compact, dim3(blocks(nQ)), dim3(256), 0, s, flag, pos, nQ, idx);
-        SD_HIP(hipGetLastError());
-        const uint32_t *perm = idx;
-        if (!(p->flags & SD_NO_QUERY_SORT) && nfb >= 4096) {
-            SD_TRY(tmp.alloc(&ord, nfb));
-            rc = query_order(sc, Q, nfb, ord, s, idx);
-            perm = ord;
-        }
-        if (!rc) rc = eval_dispatch(sc, Q, perm, nQ, p, d_out, grad_out, nullptr, false, s, nfb);
+    if (!(p->flags & SD_NO_QUERY_SORT) && nQ >= 4096) {
+        SD_TRY(tmp.alloc(&ord, nQ));
+        rc = query_order(sc, Q, nQ, ord, s, idx, nfb);
+        perm = ord;
     }
-    if (n_fallback_host) *n_fallback_host = nfb;
+    if (!rc) rc = eval_dispatch(sc, Q, perm, nQ, p, d_out, grad_out, nullptr, false, s, nQ, nfb);
     return rc;
 }

@@ -4,10 +4,14 @@
 // Forward:  x'_kj = R_k x_j + t_k for K transforms of m body points.
 // Adjoint:  with u_kj = gbar_kj * grad d(x'_kj)  (gbar = dL/dd upstream),
 //   tbar_k = sum_j u_kj,  Rbar_k = sum_j u_kj x_j^T,  xbar_j = sum_k R_k^T u_kj.
+// For the query-mesh distance D_k of the moved points (Eq. 6-8), gbar_kj =
+// w_kj * Dbar_k with w_kj = dD_k/dd_kj and Dbar_k = dL/dD_k; the product is
+// formed in the kernels (kscale = Dbar).
 // The reductions use a fixed order (per-thread strided sums over a chunk, an
 // LDS tree, then the chunk partials in order), so results are bitwise
 // reproducible.
 #include <algorithm>
+#include <string>
 
 #include "sd_internal.h"
 
@@ -33,16 +37,17 @@ k_rigid_apply(const float *__restrict__ X, int64_t m, const float *__restrict__ 
 // Rbar 9) per workgroup, written to part[k][chunk][12].
 __global__ void __launch_bounds__(kB)
 k_rigid_rt_part(const float *__restrict__ X, int64_t m, int64_t chunk, const float *__restrict__ gbar,
-                const float *__restrict__ grad, float *__restrict__ part) {
+                const float *__restrict__ kscale, const float *__restrict__ grad, float *__restrict__ part) {
     __shared__ float red[12][kB];
     const int64_t k = blockIdx.x;
+    const float ks = kscale ? kscale[k] : 1.f;
     const int64_t j0 = (int64_t)blockIdx.y * chunk, j1 = min(m, j0 + chunk);
     float acc[12];
 #pragma unroll
     for (int a = 0; a < 12; ++a) acc[a] = 0.f;
     for (int64_t j = j0 + threadIdx.x; j < j1; j += kB) {
         int64_t i = k * m + j;
-        float g = gbar[i];
+        float g = kscale ? gbar[i] * ks : gbar[i];
         float u0 = g * grad[3 * i], u1 = g * grad[3 * i + 1], u2 = g * grad[3 * i + 2];
         float x0 = X[3 * j], x1 = X[3 * j + 1], x2 = X[3 * j + 2];
         acc[0] += u0; acc[1] += u1; acc[2] += u2;
@@ -78,14 +83,15 @@ __global__ void k_rigid_rt_final(const float *__restrict__ part, int64_t K, int 
 // part[chunk][j][3]
 __global__ void __launch_bounds__(kB)
 k_rigid_x_part(const float *__restrict__ R, int64_t K, int64_t kchunk, int64_t m,
-               const float *__restrict__ gbar, const float *__restrict__ grad, float *__restrict__ part) {
+               const float *__restrict__ gbar, const float *__restrict__ kscale, const float *__restrict__ grad,
+               float *__restrict__ part) {
     int64_t j = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (j >= m) return;
     const int64_t k0 = (int64_t)blockIdx.y * kchunk, k1 = min(K, k0 + kchunk);
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
     for (int64_t k = k0; k < k1; ++k) {
         int64_t i = k * m + j;
-        float g = gbar[i];
+        float g = kscale ? gbar[i] * kscale[k] : gbar[i];
         float u0 = g * grad[3 * i], u1 = g * grad[3 * i + 1], u2 = g * grad[3 * i + 2];
         const float *r = R + 9 * k;
         a0 = fmaf(r[0], u0, fmaf(r[3], u1, fmaf(r[6], u2, a0)));
@@ -123,14 +129,14 @@ extern "C" int sd_rigid_transform(const float *X, int64_t m, const float *R, con
     return SD_OK;
 }
 
-extern "C" int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64_t K,
-                                const float *gbar, const float *grad, float *Rbar, float *tbar,
-                                float *Xbar, void *stream) {
-    if (m < 0 || K < 0) return sd::fail(SD_EINVAL, "sd_rigid_adjoint: negative size");
+namespace {
+int rigid_adjoint(const char *name, const float *X, int64_t m, const float *R, int64_t K, const float *gbar,
+                  const float *kscale, const float *grad, float *Rbar, float *tbar, float *Xbar, void *stream) {
+    if (m < 0 || K < 0) return sd::fail(SD_EINVAL, std::string(name) + ": negative size");
     if (K == 0) return SD_OK;
     if (!R || !Rbar || !tbar || (m > 0 && (!X || !gbar || !grad)))
-        return sd::fail(SD_EINVAL, "sd_rigid_adjoint: null pointer");
-    if (K > 0x7fffffff) return sd::fail(SD_EUNSUPPORTED, "sd_rigid_adjoint: too many transforms");
+        return sd::fail(SD_EINVAL, std::string(name) + ": null pointer");
+    if (K > 0x7fffffff) return sd::fail(SD_EUNSUPPORTED, std::string(name) + ": too many transforms");
     hipStream_t s = (hipStream_t)stream;
     // split each reduction so that the grid fills the chip; partials are added
     // in a fixed order (bitwise reproducible)
@@ -146,7 +152,7 @@ extern "C" int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64
     SD_TRY(tmp.alloc(&part, (int64_t)(bytes / sizeof(float))));
     if (m > 0) {
         hipLaunchKernelGGL(sd::k_rigid_rt_part, dim3((unsigned)K, (unsigned)chunks), dim3(256), 0, s, X, m, chunk,
-                           gbar, grad, part);
+                           gbar, kscale, grad, part);
         hipLaunchKernelGGL(sd::k_rigid_rt_final, dim3((unsigned)((K * 12 + 255) / 256)), dim3(256), 0, s, part, K,
                            chunks, Rbar, tbar);
     } else {
@@ -155,10 +161,24 @@ extern "C" int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64
     }
     if (want_x) {
         hipLaunchKernelGGL(sd::k_rigid_x_part, dim3((unsigned)((m + 255) / 256), (unsigned)kchunks), dim3(256), 0,
-                           s, R, K, kchunk, m, gbar, grad, part);
+                           s, R, K, kchunk, m, gbar, kscale, grad, part);
         hipLaunchKernelGGL(sd::k_rigid_x_final, dim3((unsigned)((3 * m + 255) / 256)), dim3(256), 0, s, part, m,
                            kchunks, Xbar);
     }
     SD_HIP(hipGetLastError());
     return SD_OK;
+}
+}  // namespace
+
+extern "C" int sd_rigid_adjoint(const float *X, int64_t m, const float *R, int64_t K,
+                                const float *gbar, const float *grad, float *Rbar, float *tbar,
+                                float *Xbar, void *stream) {
+    return rigid_adjoint("sd_rigid_adjoint", X, m, R, K, gbar, nullptr, grad, Rbar, tbar, Xbar, stream);
+}
+
+extern "C" int sd_rigid_qmesh_adjoint(const float *X, int64_t m, const float *R, int64_t K, const float *w,
+                                      const float *Dbar, const float *grad, float *Rbar, float *tbar,
+                                      float *Xbar, void *stream) {
+    if (K > 0 && !Dbar) return sd::fail(SD_EINVAL, "sd_rigid_qmesh_adjoint: null pointer");
+    return rigid_adjoint("sd_rigid_qmesh_adjoint", X, m, R, K, w, Dbar, grad, Rbar, tbar, Xbar, stream);
 }

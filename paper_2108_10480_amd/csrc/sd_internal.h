@@ -22,6 +22,17 @@ int fail(int code, const std::string &msg);
                               std::string(#call) + ": " + hipGetErrorString(_e));     \
     } while (0)
 
+// ---------------------------------------------------------------------------
+// Device memory: every allocation of the library goes through these, which
+// keep the bytes it holds and enforce the optional budget
+// (sd_set_memory_budget).  A refused or failed allocation returns SD_ENOMEM
+// and leaves *p null.
+// ---------------------------------------------------------------------------
+int dev_malloc(void **p, size_t bytes, const char *what);
+int dev_malloc_async(void **p, size_t bytes, hipStream_t s, const char *what);
+void dev_free(void *p);
+void dev_free_async(void *p, hipStream_t s);
+
 #define SD_TRY(expr)                        \
     do {                                    \
         int _rc = (expr);                   \
@@ -38,7 +49,7 @@ class AsyncScratch {
     AsyncScratch(const AsyncScratch &) = delete;
     AsyncScratch &operator=(const AsyncScratch &) = delete;
     ~AsyncScratch() {
-        for (size_t k = n_; k-- > 0;) (void)hipFreeAsync(ptr_[k], s_);
+        for (size_t k = n_; k-- > 0;) dev_free_async(ptr_[k], s_);
     }
     // count elements of T (at least one); SD_ENOMEM / SD_EHIP on failure
     template <class T>
@@ -46,12 +57,8 @@ class AsyncScratch {
         *p = nullptr;
         if (n_ == kMax) return fail(SD_EHIP, "AsyncScratch: too many buffers");
         size_t bytes = (size_t)(count > 1 ? count : 1) * sizeof(T);
-        hipError_t e = hipMallocAsync((void **)p, bytes, s_);
-        if (e != hipSuccess) {
-            *p = nullptr;
-            return fail(e == hipErrorOutOfMemory ? SD_ENOMEM : SD_EHIP,
-                        std::string("hipMallocAsync: ") + hipGetErrorString(e));
-        }
+        int rc = dev_malloc_async((void **)p, bytes, s_, "scratch");
+        if (rc != SD_OK) return rc;
         ptr_[n_++] = (void *)*p;
         return SD_OK;
     }
@@ -104,6 +111,7 @@ struct EvalArgs {
     uint32_t flags;
     int32_t nq;            // number of queries (bound of the entries of perm)
     int32_t nthr;          // number of threads: perm entries (nq without perm)
+    const uint32_t *nthr_dev = nullptr;  // optional device count: min(nthr, *nthr_dev) threads work
     const float *Q;
     const uint32_t *perm;  // optional query order (nullptr = identity)
     float *d_out;
@@ -122,8 +130,10 @@ void triangle_monomial_horner(int v, int e, double out[36]);
 // Sorting and scans (sort.hip)
 size_t radix_sort_temp_bytes(int64_t n);
 // Stable ascending sort of (key, val) pairs by the low `bits` bits of key.
+// With n_dev, the first min(n, *n_dev) pairs are sorted (the count read on the
+// device; n sizes the launches and the scratch).
 int radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_tmp, uint32_t *vals_tmp,
-                     int64_t n, int bits, void *temp, hipStream_t s);
+                     int64_t n, int bits, void *temp, hipStream_t s, const uint32_t *n_dev = nullptr);
 int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, void *temp,
                        hipStream_t s);
 
@@ -152,15 +162,17 @@ struct sd_scene {
 
 namespace sd {
 // Query Morton ordering used by the evaluation (eval.hip)
-// With idx, only the queries idx[0..nq) are ordered (perm gets those indices).
+// With idx, only the queries idx[0..nq) are ordered (perm gets those indices);
+// with n_dev as well, only idx[0..min(nq, *n_dev)) (a count on the device).
 int query_order(const sd_scene *sc, const float *Q, int64_t nq, uint32_t *perm, hipStream_t s,
-                const uint32_t *idx = nullptr);
+                const uint32_t *idx = nullptr, const uint32_t *n_dev = nullptr);
 // value + gradient with the query order's scratch in a static device array
 // (no allocation; at most SD_NOALLOC_MAX_QUERIES queries) (eval.hip)
 int eval_grad_noalloc(const sd_scene *sc, const float *Q, int64_t nq, const sd_params *p, float *d_out,
                       float *g_out, hipStream_t s);
 // nthr >= 0 with perm_in: nthr threads evaluate the queries perm_in[0..nthr)
-// out of nq; results land at the original query indices.
+// out of nq; results land at the original query indices.  With nthr_dev as
+// well, the launch is sized for nthr and min(nthr, *nthr_dev) threads work.
 // value + gradient for edge (nv = 2) or triangle (nv = 3) query primitives (eval.hip)
 int evalq_dispatch(const sd_scene *sc, const float *G, int nv, int64_t n, const sd_params *p, float *d_out,
                    float *g_out, hipStream_t s);
@@ -170,5 +182,5 @@ int trace_dispatch(const sd_scene *sc, const float *O, const float *U, int64_t n
                    hipStream_t s);
 int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, int64_t nq,
                   const sd_params *p, float *d_out, float *g_out, int32_t *counts, bool brute,
-                  hipStream_t s, int64_t nthr = -1);
+                  hipStream_t s, int64_t nthr = -1, const uint32_t *nthr_dev = nullptr);
 }  // namespace sd

@@ -3,7 +3,9 @@
 // ordering.  Wave64 design: each 256-thread block owns a tile of 2048 keys;
 // ranks inside a tile come from 64-lane ballots (match-any on the 8-bit digit)
 // and per-wave digit counters in LDS, so no atomics touch global memory and
-// the result is deterministic.
+// the result is deterministic.  The sort can take its key count from device
+// memory (n_dev, at most the host bound n that sizes the launches), so that a
+// count produced on the GPU never has to reach the host.
 #include "sd_internal.h"
 
 namespace sd {
@@ -21,9 +23,10 @@ __device__ inline uint64_t lanemask_lt() {
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_digit_hist(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t *__restrict__ hist,
-             int nblocks) {
+k_digit_hist(const uint64_t *__restrict__ keys, int64_t n, const uint32_t *__restrict__ n_dev, int shift,
+             uint32_t *__restrict__ hist, int nblocks) {
     __shared__ uint32_t h[kRadix];
+    if (n_dev) n = min(n, (int64_t)*n_dev);
     h[threadIdx.x] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kTile;
@@ -38,8 +41,9 @@ k_digit_hist(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t *
 __global__ void __launch_bounds__(kThreads)
 k_digit_scatter(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
                 uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, int64_t n,
-                int shift, const uint32_t *__restrict__ offs, int nblocks) {
+                const uint32_t *__restrict__ n_dev, int shift, const uint32_t *__restrict__ offs, int nblocks) {
     __shared__ uint32_t wcnt[kWaves][kRadix];
+    if (n_dev) n = min(n, (int64_t)*n_dev);
     __shared__ uint32_t goff[kRadix];
     const int lane = __lane_id();
     const int w = threadIdx.x >> 6;
@@ -188,7 +192,7 @@ size_t radix_sort_temp_bytes(int64_t n) {
 }
 
 int radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_tmp, uint32_t *vals_tmp,
-                     int64_t n, int bits, void *temp, hipStream_t s) {
+                     int64_t n, int bits, void *temp, hipStream_t s, const uint32_t *n_dev) {
     if (n <= 1) return SD_OK;
     if (n > (int64_t)0xffffffffll) return fail(SD_EUNSUPPORTED, "radix sort: more than 2^32 keys");
     int nb = (int)ceil_div(n, kTile);
@@ -201,10 +205,10 @@ int radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_tmp, uint32_
     int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
-        hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kThreads), 0, s, ka, n, shift, hist, nb);
+        hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kThreads), 0, s, ka, n, n_dev, shift, hist, nb);
         SD_TRY(exclusive_scan_u32(hist, offs, (int64_t)nb * kRadix, stemp, s));
         hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kThreads), 0, s, ka, va, kb, vb, n,
-                           shift, offs, nb);
+                           n_dev, shift, offs, nb);
         std::swap(ka, kb);
         std::swap(va, vb);
     }

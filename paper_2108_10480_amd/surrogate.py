@@ -126,17 +126,19 @@ class Surrogate:
 
 def sd_eval_surrogate(scene, sur, Q, alpha, beta=0.5, band=0.05, alpha_u=0.0, flags=0, out=None,
                       grad_out=None, routed=None):
-    """(d, grad, routed flags, number of exactly evaluated queries)."""
+    """(d, grad, routed flags, number of exactly evaluated queries as a
+    one-element int32 tensor on the device: the call does not wait for the
+    GPU; int() of it does)."""
     Qp, n = _dptr(Q, torch.float32, "Q", 3)
     d = out if out is not None else torch.empty(n, dtype=torch.float32, device=Q.device)
     g = grad_out if grad_out is not None else torch.empty((n, 3), dtype=torch.float32, device=Q.device)
     r = routed if routed is not None else torch.empty(n, dtype=torch.uint8, device=Q.device)
     p = api.params(alpha, beta, alpha_u, flags)
-    nfb = ctypes.c_int64()
+    nfb = torch.empty(1, dtype=torch.int32, device=Q.device)
     _check(lib().sd_eval_surrogate(scene.handle, sur.handle, Qp, _i64(n), ctypes.byref(p),
                                    ctypes.c_float(band), _c_p(d.data_ptr()), _c_p(g.data_ptr()),
-                                   _c_p(r.data_ptr()), ctypes.byref(nfb), _stream()))
-    return d, g, r, nfb.value
+                                   _c_p(r.data_ptr()), _c_p(nfb.data_ptr()), _stream()))
+    return d, g, r, nfb
 
 
 def cosine_lr(step, total, lr0, lr_min, warmup=0):

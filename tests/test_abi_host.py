@@ -87,3 +87,16 @@ def test_null_and_bad_arguments_rejected_on_host(libsd):
     assert libsd.sd_eval(None, None, ctypes.c_int64(0), ctypes.byref(p), None, None) == -1
     assert libsd.sd_rigid_adjoint(None, ctypes.c_int64(-1), None, ctypes.c_int64(1), None, None,
                                   None, None, None, None) == -1
+
+
+def test_memory_budget_entry_points_on_host(libsd):
+    """sd_set_memory_budget / sd_memory_in_use touch no device: the count
+    starts at zero in a process that has allocated nothing, a null output is
+    rejected, and any budget (or none) is accepted."""
+    libsd.sd_memory_in_use.restype = ctypes.c_int
+    libsd.sd_set_memory_budget.restype = ctypes.c_int
+    n = ctypes.c_int64(-7)
+    assert libsd.sd_memory_in_use(ctypes.byref(n)) == 0 and n.value == 0
+    assert libsd.sd_memory_in_use(None) == -1
+    for b in (0, 1 << 30, -1):
+        assert libsd.sd_set_memory_budget(ctypes.c_int64(b)) == 0

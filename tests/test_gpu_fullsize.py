@@ -182,6 +182,7 @@ def test_full_size_surrogate_inference_and_routing():
     band, eps = 0.05, 0.02
     sur.load(th, eps_cert=eps)
     d, g, routed, nfb = S.sd_eval_surrogate(scene, sur, Xd, 50.0, 0.5, band=band)
+    nfb = int(nfb)
     torch.cuda.synchronize()
     y, gy, d, g = y.cpu().numpy(), gy.cpu().numpy(), d.cpu().numpy(), g.cpu().numpy()
     routed = routed.cpu().numpy().astype(bool)

@@ -2,6 +2,8 @@
 
 * sd_rigid_transform against the oracle's x' = R x + t;
 * sd_rigid_adjoint against the oracle's reductions on the same (gbar, grad);
+* sd_rigid_qmesh_adjoint (upstream w * Dbar formed on the GPU) against
+  sd_rigid_adjoint on the same product;
 * the autograd function (forward sd_eval_grad, backward sd_rigid_adjoint)
   against central finite differences of the FP64 oracle (h = 1e-4, beta = 0),
   and its X gradient against the oracle gradient pulled back through R.
@@ -55,6 +57,33 @@ def test_rigid_adjoint_matches_oracle_reductions():
     # deterministic: the reductions use a fixed order
     Rb2, tb2, Xb2 = api.sd_rigid_adjoint(cuda(X), cuda(R), cuda(gbar), cuda(grad))
     assert torch.equal(Rb, Rb2) and torch.equal(tb, tb2) and torch.equal(Xb, Xb2)
+
+
+def test_query_mesh_adjoint_forms_the_weighted_upstream_on_the_gpu():
+    """sd_rigid_qmesh_adjoint (gbar_kj = w_kj Dbar_k formed in the kernels)
+    equals sd_rigid_adjoint on the FP32 product w * Dbar bit for bit (the same
+    product, then the same fixed-order reductions), and the oracle's
+    reductions on that gbar."""
+    require_gpu()
+    rng = np.random.default_rng(52)
+    K, m = 7, 3001
+    X, R = _body(m, rng), _rotations(K, rng)
+    w = rng.uniform(0.0, 2.0 / m, (K, m)).astype(np.float32)
+    Dbar = rng.standard_normal(K).astype(np.float32)
+    grad = rng.standard_normal((K * m, 3)).astype(np.float32)
+    Rq, tq, Xq = api.sd_rigid_qmesh_adjoint(cuda(X), cuda(R), cuda(w), cuda(Dbar), cuda(grad))
+    gbar = (w * Dbar[:, None]).astype(np.float32)
+    Rb, tb, Xb = api.sd_rigid_adjoint(cuda(X), cuda(R), cuda(gbar.reshape(-1)), cuda(grad))
+    assert torch.equal(Rq, Rb) and torch.equal(tq, tb) and torch.equal(Xq, Xb)
+    Rr, tr, Xr = O.rigid_adjoint(X, R, gbar.reshape(-1), grad)
+    scale = np.abs(gbar.reshape(-1)[:, None] * grad).reshape(K, m, 3).sum(1).max()
+    np.testing.assert_allclose(tq.cpu().numpy(), tr, atol=1e-5 * scale)
+    np.testing.assert_allclose(Rq.cpu().numpy(), Rr, atol=1e-5 * scale)
+    np.testing.assert_allclose(Xq.cpu().numpy(), Xr, atol=1e-5 * np.abs(Xr).max() + 1e-9)
+    with pytest.raises(ValueError):
+        api.sd_rigid_qmesh_adjoint(cuda(X), cuda(R), cuda(w), cuda(Dbar[:-1]), cuda(grad))
+    with pytest.raises(TypeError):
+        api.sd_rigid_qmesh_adjoint(cuda(X), cuda(R), cuda(w), cuda(Dbar.astype(np.float64)), cuda(grad))
 
 
 def test_rigid_adjoint_empty_and_invalid():

@@ -196,6 +196,7 @@ def test_routing_to_exact_evaluation(nq, flags):
     band, eps = 0.08, 0.02
     sur.load(th, eps_cert=eps)
     d, g, routed, nfb = S.sd_eval_surrogate(scene, sur, Xd, 50.0, 0.5, band=band, flags=flags)
+    nfb = int(nfb)
     d, g, routed = d.cpu().numpy(), g.cpu().numpy(), routed.cpu().numpy().astype(bool)
     want = np.abs(y) < np.float32(band) + np.float32(eps)
     assert np.array_equal(routed, want)
@@ -211,9 +212,11 @@ def test_routing_to_exact_evaluation(nq, flags):
     # nothing routed / everything routed
     sur.load(th, eps_cert=0.0)
     d0, _, r0, n0 = S.sd_eval_surrogate(scene, sur, Xd, 50.0, 0.5, band=0.0)
+    n0 = int(n0)
     assert n0 == 0 and not r0.any() and np.array_equal(d0.cpu().numpy(), y)
     sur.load(th, eps_cert=float("inf"))
     d1, _, r1, n1 = S.sd_eval_surrogate(scene, sur, Xd, 50.0, 0.5, band=0.05)
+    n1 = int(n1)
     assert n1 == nq and bool(r1.all())
 
 
@@ -259,6 +262,7 @@ def test_local_certificate_and_routing():
     yq = sur.forward(cuda(Xq), grad=False).cpu().numpy()
     band = np.float32(0.05)
     d, g, routed, nfb = S.sd_eval_surrogate(scene, sur, cuda(Xq), 50.0, 0.5, band=float(band))
+    nfb = int(nfb)
     cq = _cells(Xq, lo, ginv, G)
     thr = np.where(cq >= 0, band + ceps[np.maximum(cq, 0)], band + np.float32(eps)).astype(np.float32)
     want = np.abs(yq) < thr
@@ -269,6 +273,7 @@ def test_local_certificate_and_routing():
     cap = np.float32(np.median(ceps[ceps < 0.1]))
     sur.certify_cells(cuda(Xv), cuda(lab), lo, hi, grid=G, safety=safety, max_margin=float(cap))
     _, _, rc, nc = S.sd_eval_surrogate(scene, sur, cuda(Xq), 50.0, 0.5, band=float(band))
+    nc = int(nc)
     ceps_c = np.where(ceps > cap, np.float32(np.inf), ceps)
     thr_c = np.where(cq >= 0, band + ceps_c[np.maximum(cq, 0)], band + np.float32(eps)).astype(np.float32)
     want_c = np.abs(yq) < thr_c
@@ -277,4 +282,5 @@ def test_local_certificate_and_routing():
     # a global certificate drops the grid
     eps2 = sur.certify(cuda(Xv), cuda(lab), safety=safety)
     _, _, r2, n2 = S.sd_eval_surrogate(scene, sur, cuda(Xq), 50.0, 0.5, band=float(band))
+    n2 = int(n2)
     assert np.array_equal(r2.cpu().numpy().astype(bool), np.abs(yq) < band + np.float32(eps2))

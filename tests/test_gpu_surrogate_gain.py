@@ -54,6 +54,7 @@ def test_trained_surrogate_gain():
     n = 8_000_000
     Xin = torch.as_tensor(scenes.uniform_queries(n, 8, -1.5, 1.5), device="cuda")
     d, g, routed, nfb = S.sd_eval_surrogate(scene, sur, Xin, alpha, beta, band=band)
+    nfb = int(nfb)
     de, ge = api.sd_eval_grad(scene, Xin, alpha, beta)
     r = routed.bool()
     frac = nfb / n
