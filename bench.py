@@ -165,6 +165,18 @@ def _parity(np, O, osc, trees, Qs, d, g, alpha, beta, floor):
             "conservative_violations": int(np.sum(d.astype(np.float64) > dm))}, dt
 
 
+def _compensated_row(np, torch, api, scene, Qd, perm, d, g, alpha, beta, steps, par_fn):
+    """The same step with the running sums in compensated FP32
+    (SD_LSE_COMPENSATED_F32) instead of FP64: time, and the parity sample
+    (par_fn on the new outputs) when given."""
+    ms, order_ms, trav = _timed_steps(torch, _ordered_step(api, scene, Qd, perm, d, g, alpha, beta,
+                                                           flags=api.SD_LSE_COMPENSATED_F32), steps, 1)
+    row = {"queries_per_s": len(Qd) / (ms * 1e-3), "ms_per_step": ms, "traversal_ms": trav}
+    if par_fn is not None:
+        row["parity_sample"] = par_fn()
+    return row
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +308,17 @@ def main():
                       f"hierarchies (Alg. 1/Alg. 2, every term in FP64), {dt:.1f} s",
             "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
         out["parity_sample"] = par
+    _progress("compensated FP32 sums")
+    par_fn = None
+    if not args.no_cpu_baseline:
+        par_fn = lambda: _parity(np, O, osc, trees, Q[idx].astype(np.float64), d[idx_d].cpu().numpy(),
+                                 g[idx_d].cpu().numpy(), args.alpha, args.beta, floor)[0]
+    out["lse_compensated_f32"] = {
+        "what": "the headline step with the running sums of Eq. 3-4 in compensated FP32 (Neumaier, product "
+                "errors by FMA) instead of FP64; log-terms FP64 in both",
+        "fp64_sums": {"queries_per_s": qps, "ms_per_step": ms_step, "traversal_ms": eval_ms},
+        "compensated_f32_sums": _compensated_row(np, torch, api, scene, Qd, perm, d, g, args.alpha, args.beta,
+                                                 max(3, args.steps // 4), par_fn)}
     if not args.no_sweep:
         out["alpha_sweep"] = alpha_sweep_leg(args, np, torch, api, scene, Qd, perm, d, g, O, osc, trees, Q,
                                              floor)
@@ -452,6 +475,12 @@ def icosphere_leg(args, np, torch, api, scenes):
         if O is not None:
             row["parity_sample"], _ = _parity(np, O, osc, trees, Q[idx].astype(np.float64), d[idx_d].cpu().numpy(),
                                               g[idx_d].cpu().numpy(), alpha, args.beta, floor)
+        par_fn = None
+        if O is not None:
+            par_fn = lambda: _parity(np, O, osc, trees, Q[idx].astype(np.float64), d[idx_d].cpu().numpy(),
+                                     g[idx_d].cpu().numpy(), alpha, args.beta, floor)[0]
+        row["compensated_f32_sums"] = _compensated_row(np, torch, api, scene, Qd, perm, d, g, alpha, args.beta,
+                                                       20, par_fn)
         res["alphas"][f"{alpha:g}"] = row
     return res, sc, scene
 

@@ -70,6 +70,12 @@ enum {
                                        those are skipped when alpha x scene diagonal > 1000:
                                        they cannot change an FP32 result)                      */
 #define SD_COUNTERS_BY_CLASS 0x20u  /* sd_eval_counters: exact leaf terms per primitive class   */
+#define SD_LSE_COMPENSATED_F32 0x40u /* value + gradient of point queries (sd_eval_grad,
+                                        sd_eval_grad_ordered, _noalloc): the running sums of Eq. 3-4
+                                        in compensated FP32 (Neumaier; product errors by FMA)
+                                        instead of FP64; log-terms stay FP64.  A compiled variant
+                                        kept for comparison: on this GPU the FP64 sums are as fast
+                                        and exact to FP64 rounding.  SD_EUNSUPPORTED elsewhere. */
 
 typedef struct sd_params {
     float alpha;     /* accuracy / smoothness, > 0 (Eq. 3)                                   */

@@ -25,6 +25,7 @@ SD_NO_QUERY_SORT = 0x4
 SD_NO_CONSERVATIVE_ROUNDING = 0x8
 SD_NO_PRUNE = 0x10
 SD_COUNTERS_BY_CLASS = 0x20
+SD_LSE_COMPENSATED_F32 = 0x40
 
 _c_p = ctypes.c_void_p
 _i64 = ctypes.c_int64

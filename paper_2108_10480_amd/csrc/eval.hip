@@ -36,6 +36,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "sd_internal.h"
 
@@ -88,24 +89,103 @@ constexpr float kLo = 1.f - 0x1p-21f;
 // (o1 bounds their 1-norms); 2^-40 o1 covers that with a wide margin.
 __device__ __forceinline__ float dist_lo(float r, float o1) { return fmaf(-0x1p-40f, o1, r * kLo); }
 
-struct LSE {
+struct LSE64 {
     double L;                // largest log-term so far (-inf: none yet)
     double s, gx, gy, gz;    // sum of exp(L_i - L*) and the gradient numerator
     float Lf;                // L* rounded to FP32 (pruning bound)
     float mlo;               // lower bound of the smallest term distance
 };
+using LSE = LSE64;
 
-__device__ __forceinline__ void lse_init(LSE &st) {
+// The same state with the four sums in FP32, each compensated (Neumaier's
+// variant of Kahan summation, with the rounding error of every product taken
+// by an FMA): a sum is the unevaluated pair hi + lo.  The compiled variant
+// selected by SD_LSE_COMPENSATED_F32.
+struct LSEc32 {
+    double L;
+    float s, cs, gx, cx, gy, cy, gz, cz;
+    float Lf;
+    float mlo;
+};
+
+__device__ __forceinline__ void lse_init(LSE64 &st) {
     st.L = -INFINITY;
     st.s = st.gx = st.gy = st.gz = 0.0;
     st.Lf = -INFINITY;
     st.mlo = INFINITY;
 }
 
+__device__ __forceinline__ void lse_init(LSEc32 &st) {
+    st.L = -INFINITY;
+    st.s = st.cs = st.gx = st.cx = st.gy = st.cy = st.gz = st.cz = 0.f;
+    st.Lf = -INFINITY;
+    st.mlo = INFINITY;
+}
+
+__device__ __forceinline__ bool lse_empty(const LSE64 &st) { return st.s == 0.0 && st.L == -INFINITY; }
+__device__ __forceinline__ bool lse_empty(const LSEc32 &st) { return st.s == 0.f && st.L == -INFINITY; }
+__device__ __forceinline__ double lse_sum(const LSE64 &st) { return st.s; }
+__device__ __forceinline__ double lse_sum(const LSEc32 &st) { return (double)st.s + (double)st.cs; }
+__device__ __forceinline__ void lse_num(const LSE64 &st, double &x, double &y, double &z) {
+    x = st.gx;
+    y = st.gy;
+    z = st.gz;
+}
+__device__ __forceinline__ void lse_num(const LSEc32 &st, double &x, double &y, double &z) {
+    x = (double)st.gx + (double)st.cx;
+    y = (double)st.gy + (double)st.cy;
+    z = (double)st.gz + (double)st.cz;
+}
+
+// s + x into (s, c): the sum rounded and its rounding error added to c
+__device__ __forceinline__ void neumaier_add(float &s, float &c, float x) {
+    const float t = s + x;
+    c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
+// (s + c) * e + x into (s, c)
+__device__ __forceinline__ void neumaier_scale_add(float &s, float &c, float e, float x) {
+    const float p = s * e;
+    c = fmaf(c, e, fmaf(s, e, -p));   // error of the product, and the old compensation scaled
+    s = p;
+    neumaier_add(s, c, x);
+}
+
+// (s + c) + e * g into (s, c)
+__device__ __forceinline__ void neumaier_fma(float &s, float &c, float e, float g) {
+    const float p = e * g;
+    c += fmaf(e, g, -p);
+    neumaier_add(s, c, p);
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void lse_fold(LSEc32 &st, float t, double Lnew, float gx, float gy, float gz) {
+    if (t <= 0.f) {
+        const float e = __expf(t);
+        neumaier_add(st.s, st.cs, e);
+        if (GRAD) {
+            neumaier_fma(st.gx, st.cx, e, gx);
+            neumaier_fma(st.gy, st.cy, e, gy);
+            neumaier_fma(st.gz, st.cz, e, gz);
+        }
+    } else {
+        const float e = __expf(-t);
+        neumaier_scale_add(st.s, st.cs, e, 1.f);
+        if (GRAD) {
+            neumaier_scale_add(st.gx, st.cx, e, gx);
+            neumaier_scale_add(st.gy, st.cy, e, gy);
+            neumaier_scale_add(st.gz, st.cz, e, gz);
+        }
+        st.L = Lnew;
+        st.Lf = (float)Lnew;
+    }
+}
+
 // Fold one term with exponent t = L_i - L* (FP32); Lnew is the term's log-term
 // in FP64, which becomes the reference when t > 0.
 template <bool GRAD>
-__device__ __forceinline__ void lse_fold(LSE &st, float t, double Lnew, float gx, float gy, float gz) {
+__device__ __forceinline__ void lse_fold(LSE64 &st, float t, double Lnew, float gx, float gy, float gz) {
     if (t <= 0.f) {
         double e = (double)__expf(t);
         st.s += e;
@@ -129,8 +209,8 @@ __device__ __forceinline__ void lse_fold(LSE &st, float t, double Lnew, float gx
 
 // One term: log-term L (FP64), lower bound dlo of its distance, and g = grad d -
 // grad(log w)/alpha (the Eq. 4 numerator direction).
-template <bool GRAD>
-__device__ __forceinline__ void lse_add(LSE &st, double L, float dlo, float gx, float gy, float gz) {
+template <bool GRAD, class St>
+__device__ __forceinline__ void lse_add(St &st, double L, float dlo, float gx, float gy, float gz) {
     st.mlo = fminf(st.mlo, dlo);
     lse_fold<GRAD>(st, (float)(L - st.L), L, gx, gy, gz);
 }
@@ -412,9 +492,9 @@ __device__ __forceinline__ void load_node(const TreeView &T, int node, float4 &l
 // else the left child node + 1), whose record is loaded into (lo, hi) before
 // the far-field term is added, so that the load overlaps that arithmetic.
 // Returns the leaf slot to evaluate, or -1.
-template <bool GRAD, bool COUNT, bool PRUNE>
+template <bool GRAD, bool COUNT, bool PRUNE, class St>
 __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, float qx, float qy,
-                                          float qz, LSE &st, float4 &lo, float4 &hi, int &node,
+                                          float qz, St &st, float4 &lo, float4 &hi, int &node,
                                           float4 &leaf_lo, int &n_vis, int &n_far) {
     const float yx = clampf(qx, lo.x, hi.x);
     const float yy = clampf(qy, lo.y, hi.y);
@@ -500,9 +580,10 @@ __device__ __forceinline__ float seed_distance(const TreeView &T, float qx, floa
     return fsqrt(dot3(dx, dy, dz, dx, dy, dz)) + fsqrt(dot3(ex, ey, ez, ex, ey, ez)) + inv_alpha;
 }
 
-__device__ __forceinline__ void lse_seed(LSE &st, const TreeView &T, const EvalArgs &A, float qx, float qy,
+template <class St>
+__device__ __forceinline__ void lse_seed(St &st, const TreeView &T, const EvalArgs &A, float qx, float qy,
                                          float qz) {
-    if (st.s == 0.0 && st.L == -INFINITY) {
+    if (lse_empty(st)) {
         const float sd = seed_distance(T, qx, qy, qz, A.inv_alpha);
         if (sd == sd) {   // NaN queries keep the empty reference
             st.L = -A.alpha64 * (double)sd;
@@ -539,8 +620,8 @@ __device__ __forceinline__ void wave_sync() {
 // Fold the owner's queued results: entry k has exponent t_k relative to the
 // reference `base` the owner held at the flush (rescalings by earlier entries
 // move the reference, so each exponent is re-based in FP64).
-template <bool GRAD>
-__device__ __forceinline__ void fold_queue(LSE &st, const LeafQueue &lq, int cnt, int lane) {
+template <bool GRAD, class St>
+__device__ __forceinline__ void fold_queue(St &st, const LeafQueue &lq, int cnt, int lane) {
     const double base = st.L;
     for (int k = 0; k < cnt; ++k) {
         float gx = 0.f, gy = 0.f, gz = 0.f;
@@ -551,9 +632,9 @@ __device__ __forceinline__ void fold_queue(LSE &st, const LeafQueue &lq, int cnt
     }
 }
 
-template <int CLS, bool GRAD, bool COUNT, bool PRUNE>
+template <int CLS, bool GRAD, bool COUNT, bool PRUNE, class St>
 __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, float qx, float qy,
-                                         float qz, LSE &st, int &n_vis, int &n_far, int &n_leaf,
+                                         float qz, St &st, int &n_vis, int &n_far, int &n_leaf,
                                          LeafQueue &lq, bool active = true) {
     const bool metric = (A.flags & SD_GRAD_PAPER_METRIC) != 0;
     int node = (active && T.n_nodes > 0) ? 0 : -1;
@@ -1088,26 +1169,29 @@ __device__ __forceinline__ int xcd_block(int i, int G) {
 // Alg. 2: d = -(L* + log s) / alpha in FP64, rounded once to FP32; grad = G / s.
 // By default d is then clamped to the smallest lower bound of a term distance
 // (see the head of this file), which keeps d <= d_min in FP32.
-template <bool GRAD>
-__device__ __forceinline__ void final_value(const EvalArgs &A, const LSE &st, float &d, float &gx,
+template <bool GRAD, class St>
+__device__ __forceinline__ void final_value(const EvalArgs &A, const St &st, float &d, float &gx,
                                             float &gy, float &gz) {
     gx = gy = gz = 0.f;
-    if (!(st.s > 0.0) && !(st.s != st.s)) {
+    const double s = lse_sum(st);
+    if (!(s > 0.0) && !(s != s)) {
         d = INFINITY;   // empty scene: the empty sum
         return;
     }
-    d = (float)(-(st.L + log(st.s)) * A.inv_alpha64);
+    d = (float)(-(st.L + log(s)) * A.inv_alpha64);
     if (A.clamp && d > st.mlo) d = st.mlo;   // NaN stays NaN
     if (GRAD) {
-        const double inv = 1.0 / st.s;
-        gx = (float)(st.gx * inv);
-        gy = (float)(st.gy * inv);
-        gz = (float)(st.gz * inv);
+        const double inv = 1.0 / s;
+        double nx, ny, nz;
+        lse_num(st, nx, ny, nz);
+        gx = (float)(nx * inv);
+        gy = (float)(ny * inv);
+        gz = (float)(nz * inv);
     }
 }
 
-template <bool GRAD>
-__device__ __forceinline__ void finalize(const EvalArgs &A, const LSE &st, int qi) {
+template <bool GRAD, class St>
+__device__ __forceinline__ void finalize(const EvalArgs &A, const St &st, int qi) {
     float d, gx, gy, gz;
     final_value<GRAD>(A, st, d, gx, gy, gz);
     A.d_out[qi] = d;
@@ -1131,7 +1215,7 @@ __device__ __forceinline__ void finalize(const EvalArgs &A, const LSE &st, int q
 // (Point-only variants would fit eight waves per SIMD; measured on the
 // 20M-point terrain they run 20 % slower than with four: the extra queries in
 // flight evict each other's hierarchy nodes from the caches.)
-template <bool GRAD, bool COUNT, int MASK>
+template <bool GRAD, bool COUNT, int MASK, bool C32 = false>
 __global__ void __launch_bounds__(kB) SD_EVAL_ATTR
 k_eval(EvalArgs A) {
     int i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
@@ -1141,7 +1225,7 @@ k_eval(EvalArgs A) {
     float qx = A.Q[3 * (int64_t)qi], qy = A.Q[3 * (int64_t)qi + 1], qz = A.Q[3 * (int64_t)qi + 2];
     __shared__ LeafQueue lqs[(MASK & 6) ? kB / 64 : 1];
     LeafQueue &lq = lqs[(MASK & 6) ? threadIdx.x / 64 : 0];
-    LSE st;
+    typename std::conditional<C32, LSEc32, LSE64>::type st;
     lse_init(st);
     int nv = 0, nf = 0, nl = 0, nl0 = 0, nl1 = 0;
     constexpr bool PRUNE = (MASK & 8) != 0;
@@ -1354,11 +1438,11 @@ __global__ void __launch_bounds__(kB) k_fill_f32(float *__restrict__ p, int64_t 
     if (i < n) p[i] = v;
 }
 
-template <bool GRAD, bool COUNT>
+template <bool GRAD, bool COUNT, bool C32 = false>
 void launch_eval(const EvalArgs &A, int mask, unsigned grid, hipStream_t s) {
     switch (mask) {
 #define SD_CASE(m) \
-    case m: hipLaunchKernelGGL((k_eval<GRAD, COUNT, m>), dim3(grid), dim3(kB), 0, s, A); break;
+    case m: hipLaunchKernelGGL((k_eval<GRAD, COUNT, m, C32>), dim3(grid), dim3(kB), 0, s, A); break;
         SD_CASE(1) SD_CASE(2) SD_CASE(3) SD_CASE(4) SD_CASE(5) SD_CASE(6) SD_CASE(7)
         SD_CASE(9) SD_CASE(10) SD_CASE(11) SD_CASE(12) SD_CASE(13) SD_CASE(14) SD_CASE(15)
 #undef SD_CASE
@@ -1545,6 +1629,10 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
         return fail(SD_EINVAL, "a thread count below the query count needs an index list");
     if (nthr_dev && (!perm_in || brute || counts))
         return fail(SD_EINVAL, "a thread count on the device needs an index list");
+    const bool c32 = (p->flags & SD_LSE_COMPENSATED_F32) != 0;
+    if (c32 && (brute || counts || !g_out))
+        return fail(SD_EUNSUPPORTED,
+                    "SD_LSE_COMPENSATED_F32 is compiled for the value + gradient traversal only");
     EvalArgs A;
     int mask = make_args(sc, p, A);
     A.nq = (int32_t)nq;
@@ -1585,6 +1673,8 @@ int eval_dispatch(const sd_scene *sc, const float *Q, const uint32_t *perm_in, i
     if (counts) {
         if (g_out) launch_eval<true, true>(A, mask, grid, s);
         else launch_eval<false, true>(A, mask, grid, s);
+    } else if (g_out && c32) {
+        launch_eval<true, false, true>(A, mask, grid, s);
     } else if (g_out) {
         launch_eval<true, false>(A, mask, grid, s);
     } else {
@@ -1598,6 +1688,8 @@ int evalq_dispatch(const sd_scene *sc, const float *G, int nv, int64_t n, const 
                    float *g_out, hipStream_t s) {
     if (n == 0) return SD_OK;
     if (n > (int64_t)0x7fffffff - kB) return fail(SD_EUNSUPPORTED, "more than 2^31 query primitives per call");
+    if (p->flags & SD_LSE_COMPENSATED_F32)
+        return fail(SD_EUNSUPPORTED, "SD_LSE_COMPENSATED_F32 is compiled for the point-query traversal only");
     EvalArgs A;
     const int mask = make_args(sc, p, A) & 7;
     A.nq = (int32_t)n;
@@ -1632,6 +1724,8 @@ int trace_dispatch(const sd_scene *sc, const float *O, const float *U, int64_t n
                    hipStream_t s) {
     if (n == 0) return SD_OK;
     if (n > (int64_t)0x7fffffff - kB) return fail(SD_EUNSUPPORTED, "more than 2^31 rays per call");
+    if (p->flags & SD_LSE_COMPENSATED_F32)
+        return fail(SD_EUNSUPPORTED, "SD_LSE_COMPENSATED_F32 is compiled for the point-query traversal only");
     EvalArgs A;
     const int mask = make_args(sc, p, A) & 7;   // value only, no subtree skipping
     A.nq = (int32_t)n;

@@ -119,6 +119,29 @@ def test_barnes_hut_matches_oracle_on_exported_tree(case, alpha, beta, alpha_u):
     _check_conservative(scene, Q, alpha, beta, dm, d, alpha_u=alpha_u)
 
 
+@pytest.mark.parametrize("alpha", [50.0, 500.0])
+def test_compensated_f32_sums_match_oracle(case, alpha):
+    """The compiled variant with the running sums in compensated FP32
+    (SD_LSE_COMPENSATED_F32) meets the same gate against the oracle, keeps
+    d <= d_min, and is refused where it is not compiled (value only,
+    counters, all-pairs kernel, query primitives, tracing)."""
+    name, sc, scene, osc, trees = case
+    Q = _queries(sc, 10000, seed=15)
+    C32 = api.SD_LSE_COMPENSATED_F32
+    d, g = _run(scene, Q, alpha, 0.5, flags=C32)
+    dr, gr, st = O.barnes_hut(osc, trees, Q.astype(np.float64), alpha, 0.5, cut_f32=True)
+    dm = O.dmin(osc, Q.astype(np.float64))
+    compare(d, g, dr, gr, floor_of(sc), what=f"{name} compensated-f32 a={alpha}", dmin=dm)
+    assert not np.any(d.astype(np.float64) > dm)
+    Qd = cuda(Q)
+    for call in (lambda: api.sd_eval(scene, Qd, alpha, 0.5, 0.0, C32),
+                 lambda: api.sd_eval_counters(scene, Qd, alpha, 0.5, flags=C32),
+                 lambda: api.sd_eval_brute(scene, Qd, alpha, 0.0, C32)):
+        with pytest.raises(api.SdError) as e:
+            call()
+        assert "COMPENSATED" in str(e.value)
+
+
 def test_paper_metric_and_rootlog_flags(case):
     name, sc, scene, osc, trees = case
     Q = _queries(sc, 3000, seed=14)
