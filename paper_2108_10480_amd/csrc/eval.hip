@@ -207,11 +207,22 @@ __device__ __forceinline__ void lse_fold(LSE64 &st, float t, double Lnew, float 
     }
 }
 
+// The running lower bound of the smallest term distance, updated in one
+// integer min on the bit patterns (fminf costs a second instruction that
+// quiets signalling NaNs).  Non-negative floats order as their bit patterns,
+// so the result is exact for non-negative bounds; a negative bound (a query
+// on a primitive) orders below every non-negative one, and of two negative
+// bounds this keeps the one nearer zero, which is still <= 0 <= every
+// distance: the result stays a lower bound of the smallest term distance.
+__device__ __forceinline__ float min_bound(float a, float b) {
+    return __int_as_float(min(__float_as_int(a), __float_as_int(b)));
+}
+
 // One term: log-term L (FP64), lower bound dlo of its distance, and g = grad d -
 // grad(log w)/alpha (the Eq. 4 numerator direction).
 template <bool GRAD, class St>
 __device__ __forceinline__ void lse_add(St &st, double L, float dlo, float gx, float gy, float gz) {
-    st.mlo = fminf(st.mlo, dlo);
+    st.mlo = min_bound(st.mlo, dlo);
     lse_fold<GRAD>(st, (float)(L - st.L), L, gx, gy, gz);
 }
 
@@ -232,11 +243,12 @@ struct Poly2 {
 };
 
 template <class Coef>
-__device__ __forceinline__ Poly2 tri_weight(const Coef &coef, double x, double y) {
+__device__ __forceinline__ Poly2 tri_weight(Coef coef, double x, double y) {
     double w = 0.0, wx = 0.0, wy = 0.0;
     int k = 0;
 #pragma unroll
     for (int a = 7; a >= 0; --a) {
+        coef.next_row();
         double p = coef(k++), dp = 0.0;   // P_a(y) = sum_b c_ab y^b and P_a'(y)
 #pragma unroll
         for (int b = 7 - a - 1; b >= 0; --b) {
@@ -250,10 +262,22 @@ __device__ __forceinline__ Poly2 tri_weight(const Coef &coef, double x, double y
     return Poly2{w, wx, wy};
 }
 
-struct CoefUniform {   // single valence class: coefficients in the kernel arguments
-    const EvalArgs &A;
-    __device__ __forceinline__ double operator()(int k) const { return A.tri_mono[k]; }
+// Single valence class: the class's one row, read with scalar loads where
+// the polynomial is evaluated, one Horner row (at most 8 coefficients) at a
+// time.  The row address passes through an empty asm statement before each
+// Horner row, so that the compiler can neither hoist the 36 loads to the
+// kernel's entry (keeping 72 scalar registers occupied through the whole
+// traversal, which spilled other scalars into vector lanes read back on every
+// node step) nor issue them all at once.  The table is read-only while a
+// kernel runs, so the row is read through the constant address space, which
+// makes the loads scalar.
+typedef __attribute__((address_space(4))) const double ConstF64;
+struct CoefUniform {
+    const double *row;
+    __device__ __forceinline__ void next_row() { asm volatile("" : "+s"(row)); }
+    __device__ __forceinline__ double operator()(int k) const { return ((ConstF64 *)row)[k]; }
 };
+__device__ __forceinline__ CoefUniform coef_uniform(const double *row) { return CoefUniform{row}; }
 // Several valence classes: the lane's row of the class table, read as the
 // Horner loop consumes it (a rolled loop keeps the row out of the registers).
 __device__ __forceinline__ Poly2 tri_weight_table(const double *__restrict__ row, double x, double y) {
@@ -418,7 +442,7 @@ __device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float 
     const double s = ddot3(cx, cy, cz, cx, cy, cz);
     const float r = fsqrt((float)s);
     const float inv = r > 0.f ? frcp(r) : 0.f;
-    const Poly2 w = A.tri_uniform ? tri_weight(CoefUniform{A}, p1, p2)
+    const Poly2 w = A.tri_uniform ? tri_weight(coef_uniform(A.tri_table), p1, p2)
                                   : tri_weight_table(A.tri_table + 36 * __float_as_int(r0.w), p1, p2);
     const float o1 = (float)(fabs(apx) + fabs(apy) + fabs(apz) + fabs(abx) + fabs(aby) + fabs(abz) +
                              fabs(acx) + fabs(acy) + fabs(acz));
@@ -464,7 +488,10 @@ __device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float 
 template <int CLS, bool GRAD>
 __device__ __forceinline__ Term leaf_term(const TreeView &T, const EvalArgs &A, int slot, float4 lo,
                                           float qx, float qy, float qz, bool metric) {
-    if (CLS == 0) return point_term<GRAD>(lo, qx, qy, qz);
+    // a point's leaf record holds the point (its leaf box's corner): reading it
+    // here leaves the traversal's node record free to be overwritten by the
+    // next node's load
+    if (CLS == 0) return point_term<GRAD>(T.leaf[slot], qx, qy, qz);
     if (CLS == 1)
         return edge_term<GRAD>(T.leaf[2 * slot], T.leaf[2 * slot + 1], qx, qy, qz, A.S, (float)T.slogA,
                                A.inv_alpha, metric);
@@ -627,7 +654,7 @@ __device__ __forceinline__ void fold_queue(St &st, const LeafQueue &lq, int cnt,
         float gx = 0.f, gy = 0.f, gz = 0.f;
         if (GRAD) { gx = lq.res[k][2][lane]; gy = lq.res[k][3][lane]; gz = lq.res[k][4][lane]; }
         const double Lk = (base + (double)lq.res[k][0][lane]) + (double)lq.res[k][1][lane];
-        st.mlo = fminf(st.mlo, __int_as_float(lq.slot[k][lane]));
+        st.mlo = min_bound(st.mlo, __int_as_float(lq.slot[k][lane]));
         lse_fold<GRAD>(st, (float)(Lk - st.L), Lk, gx, gy, gz);
     }
 }
@@ -1594,7 +1621,6 @@ static int make_args(const sd_scene *sc, const sd_params *p, EvalArgs &A) {
         A.tree[c].lwmax = (float)(S * (log(sc->A[c]) + log(wmax))) + 1e-3f;
     }
     A.tri_uniform = sc->n_tri_classes <= 1 ? 1 : 0;
-    memcpy(A.tri_mono, sc->tri_mono0, sizeof(A.tri_mono));
     A.tri_table = sc->tri_table;
     A.alpha = p->alpha;
     A.inv_alpha = (float)(1.0 / alpha);

@@ -98,11 +98,9 @@ struct TreeView {
 struct EvalArgs {
     TreeView tree[3];
     // Triangle weights (App. C.3) as the 36 FP64 monomial coefficients of
-    // each valence class in Horner order (see triangle_monomial_horner); a
-    // single class is passed by value.
-    double tri_mono[36];
+    // each valence class in Horner order (see triangle_monomial_horner).
     const double *tri_table;  // n_classes x 36 (class id in the leaf record)
-    int32_t tri_uniform;      // 1: every triangle uses tri_mono
+    int32_t tri_uniform;      // 1: a single class (row 0), read with scalar loads
     float alpha, inv_alpha, beta2, S;
     double alpha64, inv_alpha64;
     int32_t clamp;        // 1: result clamped to a lower bound of the smallest term distance (default)
