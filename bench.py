@@ -207,6 +207,8 @@ def main():
                     help="near/far switch discrepancy beta 0.5 vs 0.5001 on the street points (Sec. 4.3 analogue)")
     ap.add_argument("--sur-train", type=int, default=20_000_000, help="surrogate training samples")
     ap.add_argument("--sur-epochs", type=int, default=80)
+    ap.add_argument("--sur-c5-epochs", type=int, default=40, help="surrogate epochs on the terrain scene")
+    ap.add_argument("--no-surrogate-c5", action="store_true", help="skip the surrogate on the terrain scene")
     ap.add_argument("--sur-nq", type=int, default=16_000_000, help="surrogate inference queries")
     ap.add_argument("--sur-oracle", type=int, default=20000, help="oracle-checked queries of the surrogate path")
     ap.add_argument("--sur-grid", type=int, default=32, help="cells per axis of the local certificate")
@@ -319,6 +321,9 @@ def main():
         "fp64_sums": {"queries_per_s": qps, "ms_per_step": ms_step, "traversal_ms": eval_ms},
         "compensated_f32_sums": _compensated_row(np, torch, api, scene, Qd, perm, d, g, args.alpha, args.beta,
                                                  max(3, args.steps // 4), par_fn)}
+    if not args.no_surrogate and not args.no_surrogate_c5:
+        _progress("surrogate on the terrain scene")
+        out["surrogate_terrain"] = surrogate_leg(args, sc, scene, np, torch, api, scenes, terrain=True, Xin=Qd)
     if not args.no_sweep:
         out["alpha_sweep"] = alpha_sweep_leg(args, np, torch, api, scene, Qd, perm, d, g, O, osc, trees, Q,
                                              floor)
@@ -790,25 +795,51 @@ SUR_FWD_MACS = 128 * 256 + 3 * 256 * 256 + 256
 SUR_BWD_MACS = 128 * 256 + 3 * 256 * 256
 
 
-def surrogate_leg(args, sc, scene, np, torch, api, scenes):
-    """Learned surrogate on the same scene: train on labels from the exact
-    evaluation, certify on held-out uniform queries, then answer uniform
-    queries with routing of the certified band to Barnes-Hut.  Compared with
-    Barnes-Hut alone on the same queries."""
+def surrogate_leg(args, sc, scene, np, torch, api, scenes, terrain=False, Xin=None):
+    """Learned surrogate on one scene: train on labels from the exact
+    evaluation, certify on held-out queries, then answer the scene's queries
+    with routing of the certified band to Barnes-Hut, compared with
+    Barnes-Hut alone on the same queries.  The frontier of the fixed network:
+    validation error along training, and fallback fraction / speed / error
+    outside the band against the cap on a cell's certified margin."""
     from paper_2108_10480_amd import surrogate as S
-    alpha, beta, band = ICO_ALPHAS[0], args.beta, 0.05
+    beta, band = args.beta, 0.05
+    if terrain:
+        alpha, epochs = args.alpha, args.sur_c5_epochs
+        lo, hi = scenes.scene_aabb(sc)
+        lo, hi = lo - 0.1 * (hi - lo), hi + 0.1 * (hi - lo)
+        Xtr_h = scenes.terrain_surrogate_samples(sc, args.sur_train, seed=6)
+        Xva_h = scenes.terrain_queries(sc, 2_000_000, seed=7)
+        what = f"terrain scene, {len(Xin)} headline queries (uniform in the scene box enlarged by 10 %)"
+    else:
+        alpha, epochs = ICO_ALPHAS[0], args.sur_epochs
+        lo, hi = np.full(3, -1.5), np.full(3, 1.5)
+        Xtr_h = scenes.surrogate_samples(sc, args.sur_train, seed=6)
+        Xva_h = scenes.uniform_queries(2_000_000, 7, -1.5, 1.5)
+        Xin = torch.as_tensor(scenes.uniform_queries(args.sur_nq, 8, -1.5, 1.5), device="cuda")
+        what = f"same scene, {args.sur_nq} queries uniform in [-1.5,1.5]^3"
+    lo, hi = tuple(float(x) for x in lo), tuple(float(x) for x in hi)
     ev = lambda: torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    Xtr = torch.as_tensor(scenes.surrogate_samples(sc, args.sur_train, seed=6), device="cuda")
+    Xtr = torch.as_tensor(Xtr_h, device="cuda")
+    del Xtr_h
     ytr = api.sd_eval(scene, Xtr, alpha, beta)
-    Xva = torch.as_tensor(scenes.uniform_queries(2_000_000, 7, -1.5, 1.5), device="cuda")
+    Xva = torch.as_tensor(Xva_h, device="cuda")
     yva = api.sd_eval(scene, Xva, alpha, beta)
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
     sur = S.Surrogate(scenes.fourier_matrix(11, sigma=[0.5, 1.0, 2.0, 4.0]), scenes.surrogate_init(12),
                       max_batch=65536)
+    curve = []
+
+    def on_epoch(e, k):
+        if e in (1, 2, 5, 10, 20, 40, 80, epochs):
+            err = (sur.forward(Xva, grad=False) - yva).abs()
+            curve.append({"epoch": e, "steps": k, "max_abs_err": float(err.max()),
+                          "p99_abs_err": float(torch.quantile(err[:1_000_000], 0.99)),
+                          "rmse": float((err ** 2).mean().sqrt())})
     t0 = time.perf_counter()
-    losses = S.train(sur, Xtr, ytr, args.sur_epochs, batch=65536, lr0=3e-3, lr_min=1e-5, seed=13)
+    losses = S.train(sur, Xtr, ytr, epochs, batch=65536, lr0=3e-3, lr_min=1e-5, seed=13, on_epoch=on_epoch)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     steps = len(losses)
@@ -817,8 +848,7 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
     yv = sur.forward(Xva, grad=False)
     verr = (yv - yva).abs()
 
-    n = args.sur_nq
-    Xin = torch.as_tensor(scenes.uniform_queries(n, 8, -1.5, 1.5), device="cuda")
+    n = len(Xin)
     d = torch.empty(n, device="cuda")
     g = torch.empty((n, 3), device="cuda")
     routed = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -868,26 +898,29 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
             "routed_vs_exact_max_abs_diff": float(e_routed.max()) if e_routed.numel() else 0.0,
         }
 
-    # global certificate (one margin everywhere), then a local one (32^3 cells)
+    # global certificate (one margin everywhere), then a local one (cells),
+    # then the local one with the cells' margins capped (cells above the cap
+    # route every query): the speed / error frontier of this network
     ms_sur, nfb, keep, glob = routed_run()
-    eps_local = sur.certify_cells(Xva, yva, lo=(-1.5, -1.5, -1.5), hi=(1.5, 1.5, 1.5), grid=args.sur_grid,
-                                  safety=1.5)
+    sur.certify_cells(Xva, yva, lo=lo, hi=hi, grid=args.sur_grid, safety=1.5)
     _, _, keep_local, loc = routed_run()
-    # the same local certificate with the 1e-3 target enforced by routing
-    sur.certify_cells(Xva, yva, lo=(-1.5, -1.5, -1.5), hi=(1.5, 1.5, 1.5), grid=args.sur_grid, safety=1.5,
-                      max_margin=1e-3)
-    _, _, _, gate = routed_run()
-    sur.certify_cells(Xva, yva, lo=(-1.5, -1.5, -1.5), hi=(1.5, 1.5, 1.5), grid=args.sur_grid, safety=1.5)
+    frontier = []
+    for cap in (1e-3, 3e-3, 1e-2, 3e-2):
+        sur.certify_cells(Xva, yva, lo=lo, hi=hi, grid=args.sur_grid, safety=1.5, max_margin=cap)
+        _, _, _, row = routed_run()
+        frontier.append(dict(row, max_margin=cap))
+    gate = frontier[0]
+    sur.certify_cells(Xva, yva, lo=lo, hi=hi, grid=args.sur_grid, safety=1.5)
     routed_run()
     flops = n * 2.0 * (SUR_FWD_MACS + SUR_BWD_MACS)
     res = {
-        "workload": f"same scene, {n} queries uniform in [-1.5,1.5]^3, alpha={alpha:g}, beta={beta:g}, "
-                    f"band={band} + certified margin",
+        "workload": f"{what}, alpha={alpha:g}, beta={beta:g}, band={band} + certified margin",
         "network": "3 -> 64 Fourier frequencies (sigma 0.5/1/2/4) -> 4 x 256 SiLU -> 1, BF16 weights, "
                    "FP32 accumulation",
-        "train": {"samples": args.sur_train, "epochs": args.sur_epochs, "steps": steps, "seconds": t_train,
+        "train": {"samples": args.sur_train, "epochs": epochs, "steps": steps, "seconds": t_train,
                   "label_seconds": t_label, "loss_last": float(np.mean(losses[-50:])),
                   "ms_per_step": 1e3 * t_train / steps},
+        "training_curve": curve,
         "eps_cert": eps,
         "validation": {"n": int(Xva.shape[0]), "max_abs_err": float(verr.max()),
                        "rmse": float((verr ** 2).mean().sqrt()),
@@ -897,17 +930,19 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
         "ms": {"barnes_hut": ms_bh, "mlp_value_grad": ms_mlp},
         "global_certificate": glob,
         "local_certificate": dict(loc, grid=args.sur_grid),
-        "local_certificate_1e-3_target": dict(gate, grid=args.sur_grid, max_margin=1e-3),
+        "local_certificate_1e-3_target": dict(gate, grid=args.sur_grid),
+        "frontier_by_margin_cap": frontier,
         "roofline": {"bound": "mfma", "kernel": "k_mlp_grad (value + input gradient)",
                      "achieved": flops / (ms_mlp * 1e-3) / 1e12, "peak": MFMA_BF16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": flops / (ms_mlp * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,
                      "hbm_bytes_per_query": 12 + 16,
-                     "traffic": _traffic(os.path.join(ROOT, "paper_2108_10480_amd", "csrc", "mlp.hip"),
-                                         "traffic_k_mlp_grad_4M.json", n),
+                     "traffic": (None if terrain else
+                                 _traffic(os.path.join(ROOT, "paper_2108_10480_amd", "csrc", "mlp.hip"),
+                                          "traffic_k_mlp_grad_4M.json", n)),
                      "kernel_ms": ms_mlp},
     }
     keep = keep_local
-    if args.sur_oracle and not args.no_cpu_baseline:
+    if args.sur_oracle and not args.no_cpu_baseline and not terrain:
         from oracle import oracle as O
         rng = np.random.default_rng(321)
         idx = torch.as_tensor(np.sort(rng.choice(n, size=min(args.sur_oracle, n), replace=False)), device="cuda")
@@ -920,6 +955,7 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes):
         res["vs_oracle_outside_band"] = {"n": int(keep_s.sum()),
                                          "max_abs_err": float(eo.max()) if eo.size else None,
                                          "p99_abs_err": float(np.quantile(eo, 0.99)) if eo.size else None}
+    sur.free()
     return res
 
 

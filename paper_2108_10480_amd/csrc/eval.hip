@@ -1245,8 +1245,17 @@ __device__ __forceinline__ void finalize(const EvalArgs &A, const St &st, int qi
 template <bool GRAD, bool COUNT, int MASK, bool C32 = false>
 __global__ void __launch_bounds__(kB) SD_EVAL_ATTR
 k_eval(EvalArgs A) {
-    int i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
-    if (i >= (A.nthr_dev ? min(A.nthr, (int)min(*A.nthr_dev, 0x7fffffffu)) : A.nthr)) return;
+    // With a thread count on the device the launch is sized for its upper
+    // bound: the blocks with work are the first ceil(count / kB), spread over
+    // the XCDs by the same mapping sized for them, and the rest exit.
+    int nthr = A.nthr, G = gridDim.x;
+    if (A.nthr_dev) {
+        nthr = min(nthr, (int)min(*A.nthr_dev, 0x7fffffffu));
+        G = (nthr + kB - 1) / kB;
+        if ((int)blockIdx.x >= G) return;
+    }
+    int i = xcd_block(blockIdx.x, G) * kB + threadIdx.x;
+    if (i >= nthr) return;
     int qi = A.perm ? (int)A.perm[i] : i;
     if ((unsigned)qi >= (unsigned)A.nq) return;
     float qx = A.Q[3 * (int64_t)qi], qy = A.Q[3 * (int64_t)qi + 1], qz = A.Q[3 * (int64_t)qi + 2];

@@ -260,6 +260,24 @@ def surrogate_samples(scene, n, seed=6, near_frac=0.7, offset=0.5, box=1.5):
     return _f32(X[rng.permutation(n)])
 
 
+def terrain_surrogate_samples(scene, n, seed=6, near_frac=0.7, sigma=(0.01, 0.05, 0.2)):
+    """Training points for the terrain scene: a fraction near_frac at random
+    scene vertices (terrain points, net and torus vertices) moved by an
+    isotropic Gaussian offset whose scale is drawn from `sigma`, the rest
+    uniform in the query box (the scene box enlarged by 10 % of its extent on
+    every side, as terrain_queries)."""
+    rng = np.random.default_rng(seed)
+    n_near = int(round(n * near_frac))
+    V = scene.V
+    base = V[rng.integers(0, len(V), n_near)].astype(np.float64)
+    s = np.asarray(sigma, np.float64)[rng.integers(0, len(sigma), n_near)]
+    near = base + rng.standard_normal((n_near, 3)) * s[:, None]
+    lo, hi = scene_aabb(scene)
+    far = rng.uniform(lo - 0.1 * (hi - lo), hi + 0.1 * (hi - lo), (n - n_near, 3))
+    X = np.concatenate([near, far])
+    return _f32(X[rng.permutation(n)])
+
+
 def epoch_order(n, epoch, seed=13):
     """Shuffled sample order of one training epoch, int32."""
     return _i32(np.random.default_rng([seed, epoch]).permutation(n))

@@ -149,9 +149,11 @@ def cosine_lr(step, total, lr0, lr_min, warmup=0):
     return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * min(t, 1.0)))
 
 
-def train(sur, X, labels, epochs, batch=65536, lr0=3e-3, lr_min=1e-5, seed=13, log_every=0, warmup=0):
+def train(sur, X, labels, epochs, batch=65536, lr0=3e-3, lr_min=1e-5, seed=13, log_every=0, warmup=0,
+          on_epoch=None):
     """Adam over `epochs` passes of (X, labels) (device tensors) in seeded
-    shuffled order; returns the per-step losses (host array)."""
+    shuffled order; returns the per-step losses (host array).  on_epoch(e, k),
+    when given, runs after epoch e (1-based) with k steps done."""
     n = X.shape[0]
     steps_per_epoch = n // batch
     if steps_per_epoch == 0:
@@ -168,4 +170,6 @@ def train(sur, X, labels, epochs, batch=65536, lr0=3e-3, lr_min=1e-5, seed=13, l
             k += 1
         if log_every and (ep + 1) % log_every == 0:
             print(f"epoch {ep + 1}/{epochs} loss {float(losses[k - 1]):.3e}", flush=True)
+        if on_epoch is not None:
+            on_epoch(ep + 1, k)
     return losses.cpu().numpy()
