@@ -941,6 +941,11 @@ def surrogate_leg(args, sc, scene, np, torch, api, scenes, terrain=False, Xin=No
                                           "traffic_k_mlp_grad_4M.json", n)),
                      "kernel_ms": ms_mlp},
     }
+    tr = res["roofline"]["traffic"]
+    if tr is not None:
+        gbs = tr / (ms_mlp * 1e-3) / 1e9
+        res["roofline"]["hbm_measured"] = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                           "frac": gbs / HBM_PEAK_GBS}
     keep = keep_local
     if args.sur_oracle and not args.no_cpu_baseline and not terrain:
         from oracle import oracle as O
