@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--beta", type=float, default=0.5)
     ap.add_argument("--scale", type=float, default=1.0,
                     help="headline scene size relative to 20M points, 1M triangles, 200k edges, 32M queries")
-    ap.add_argument("--cpu-sample", type=int, default=2_000_000,
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000,
                     help="queries of the headline workload timed on the FP64 oracle and checked against it")
     ap.add_argument("--headline-only", action="store_true", help="only the headline workload (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -196,14 +196,14 @@ def main():
     ap.add_argument("--rigid-steps", type=int, default=5)
     ap.add_argument("--sweep-oracle", type=int, default=20_000,
                     help="queries of each sweep alpha checked against the oracle")
-    ap.add_argument("--beta-ablation", action="store_true",
+    ap.add_argument("--beta-ablation", action=argparse.BooleanOptionalAction, default=True,
                     help="sphere-trace renders of vertex, edge and triangle scenes over beta (Sec. 4.3 analogue)")
     ap.add_argument("--ablation-res", type=int, default=256, help="image side of the beta ablation renders")
-    ap.add_argument("--prims", action="store_true",
+    ap.add_argument("--prims", action=argparse.BooleanOptionalAction, default=True,
                     help="edges and triangles as query primitives on the icosphere scene (Sec. 3.4)")
-    ap.add_argument("--contact", action="store_true",
+    ap.add_argument("--contact", action=argparse.BooleanOptionalAction, default=True,
                     help="rigid-body contact steps of the street body dropped on the street (Sec. 4.5)")
-    ap.add_argument("--switch-study", action="store_true",
+    ap.add_argument("--switch-study", action=argparse.BooleanOptionalAction, default=True,
                     help="near/far switch discrepancy beta 0.5 vs 0.5001 on the street points (Sec. 4.3 analogue)")
     ap.add_argument("--sur-train", type=int, default=20_000_000, help="surrogate training samples")
     ap.add_argument("--sur-epochs", type=int, default=80)
