@@ -226,6 +226,43 @@ __device__ __forceinline__ void lse_add(St &st, double L, float dlo, float gx, f
     lse_fold<GRAD>(st, (float)(L - st.L), L, gx, gy, gz);
 }
 
+// A far-field term: log-term L, distance lower bound dlo, and the direction
+// given as the exact FP64 difference u = q - y_B with 1/D: the gradient
+// numerator takes (e / D) u, one FP32 product and three FP64 FMAs, instead of
+// forming and converting an FP32 direction.
+template <bool GRAD>
+__device__ __forceinline__ void lse_add_far(LSE64 &st, double L, float dlo, double ux, double uy, double uz,
+                                            float inv) {
+    st.mlo = min_bound(st.mlo, dlo);
+    const float t = (float)(L - st.L);
+    if (t <= 0.f) {
+        const float e = __expf(t);
+        st.s += (double)e;
+        if (GRAD) {
+            const double ei = (double)(e * inv);
+            st.gx = fma(ei, ux, st.gx);
+            st.gy = fma(ei, uy, st.gy);
+            st.gz = fma(ei, uz, st.gz);
+        }
+    } else {
+        const double e = (double)__expf(-t);
+        st.s = fma(st.s, e, 1.0);
+        if (GRAD) {
+            const double i64 = (double)inv;
+            st.gx = fma(st.gx, e, ux * i64);
+            st.gy = fma(st.gy, e, uy * i64);
+            st.gz = fma(st.gz, e, uz * i64);
+        }
+        st.L = L;
+        st.Lf = (float)L;
+    }
+}
+template <bool GRAD>
+__device__ __forceinline__ void lse_add_far(LSEc32 &st, double L, float dlo, double ux, double uy, double uz,
+                                            float inv) {
+    lse_add<GRAD>(st, L, dlo, (float)ux * inv, (float)uy * inv, (float)uz * inv);
+}
+
 // clamp(q, lo, hi) in one v_med3_f32 (lo <= hi for every box)
 __device__ __forceinline__ float clampf(float q, float lo, float hi) {
     return __builtin_amdgcn_fmed3f(q, lo, hi);
@@ -563,8 +600,13 @@ __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, 
         const float inv = frcp(D);
         const double ux = (double)qx - (double)yx, uy = (double)qy - (double)yy, uz = (double)qz - (double)yz;
         const double D64 = sqrt_newton_pos(ddot3(ux, uy, uz, ux, uy, uz), D, inv);
-        const double L = fma(-A.alpha64, D64, (double)logn + T.slogA);
-        lse_add<GRAD>(st, L, D * kLo, dx * inv, dy * inv, dz * inv);
+        // log n_B is the payload itself: for an internal node it is log n_B;
+        // for a leaf (one primitive, log 1 = 0) it is 0x80000000 | slot with
+        // slot < 2^26 (the build's limit), which read as an FP32 number is
+        // negative and below 2^-119 in magnitude, far below the rounding of
+        // any log-term, so no select is needed here
+        const double L = fma(-A.alpha64, D64, (double)__int_as_float(pay) + T.slogA);
+        lse_add_far<GRAD>(st, L, D * kLo, ux, uy, uz, inv);
         if (COUNT) ++n_far;
     }
     return slot;
