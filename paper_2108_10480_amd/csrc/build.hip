@@ -260,7 +260,13 @@ k_refit(const float4 *__restrict__ plo, const float4 *__restrict__ phi,
 }
 
 // log(count) from FP64, rounded to the nearest float
-__device__ inline float log_count(int64_t c) { return (float)log((double)c); }
+// log n_B in fixed point with kLogFracBits fractional bits: exact to 2^-27
+// (an FP32 log n_B would be off by up to 2^-21 for n_B near 2^26, i.e. a
+// relative error of 5e-7 in a far-field weight); n_B <= 2^26 keeps the value
+// below 18.03 * 2^26 < 2^31, a non-negative int32 (leaves store a negative one)
+__device__ inline int32_t log_count_fx(int64_t c) {
+    return __double2int_rn(log((double)c) * (double)(1 << kLogFracBits));
+}
 
 __global__ void __launch_bounds__(kB)
 k_dfs_layout(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ first,
@@ -286,7 +292,7 @@ k_dfs_layout(int64_t n, const int32_t *__restrict__ left, const int32_t *__restr
     int32_t esc32 = esc >= total ? -1 : (int32_t)esc;
     float4 a = blo[x], b = bhi[x];
     a.w = __int_as_float(esc32);
-    b.w = leaf ? __int_as_float((int32_t)(0x80000000u | (uint32_t)l)) : log_count(cnt);
+    b.w = __int_as_float(leaf ? (int32_t)(0x80000000u | (uint32_t)l) : log_count_fx(cnt));
     out_lo[2 * pos] = a;   // records interleaved: lo, hi of a node share a cache line
     out_hi[2 * pos] = b;
 }

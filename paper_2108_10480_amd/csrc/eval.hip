@@ -570,7 +570,6 @@ __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, 
     const int esc = __float_as_int(lo.w);
     const int pay = __float_as_int(hi.w);
     if (COUNT) ++n_vis;
-    const float logn = pay < 0 ? 0.f : hi.w;
     // Negligible subtree: every term below this node is at most
     // n_B W_max exp(-alpha D) (D <= each d_i), i.e. its exponent relative to
     // the running maximum is below -A.prune (64: < 1e-27 of the sum), so it
@@ -578,6 +577,7 @@ __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, 
     // D > (log n_B + log W_max - L* + prune) / alpha, tested on squares.
     bool skip = false;
     if (PRUNE) {
+        const float logn = (float)max(pay, 0) * (1.f / (1 << kLogFracBits));
         const float thr = (logn + T.lwmax - st.Lf + A.prune) * A.inv_alpha;
         skip = thr < 0.f || D2 > thr * thr;
     }
@@ -600,12 +600,10 @@ __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, 
         const float inv = frcp(D);
         const double ux = (double)qx - (double)yx, uy = (double)qy - (double)yy, uz = (double)qz - (double)yz;
         const double D64 = sqrt_newton_pos(ddot3(ux, uy, uz, ux, uy, uz), D, inv);
-        // log n_B is the payload itself: for an internal node it is log n_B;
-        // for a leaf (one primitive, log 1 = 0) it is 0x80000000 | slot with
-        // slot < 2^26 (the build's limit), which read as an FP32 number is
-        // negative and below 2^-119 in magnitude, far below the rounding of
-        // any log-term, so no select is needed here
-        const double L = fma(-A.alpha64, D64, (double)__int_as_float(pay) + T.slogA);
+        // log n_B from the payload's fixed point (a leaf's negative payload
+        // gives log 1 = 0)
+        const double L = fma(-A.alpha64, D64,
+                             fma((double)max(pay, 0), 1.0 / (1 << kLogFracBits), T.slogA));
         lse_add_far<GRAD>(st, L, D * kLo, ux, uy, uz, inv);
         if (COUNT) ++n_far;
     }
@@ -1112,7 +1110,6 @@ __device__ __forceinline__ int node_visit_q(const TreeView &T, const EvalArgs &A
     float diag2 = dot3(ex, ey, ez, ex, ey, ez);
     int esc = __float_as_int(lo.w);
     int pay = __float_as_int(hi.w);
-    float logn = pay < 0 ? 0.f : hi.w;
     bool far = diag2 < A.beta2 * D2;
     bool leaf = !far && pay < 0;
     int slot = -1;
@@ -1127,7 +1124,7 @@ __device__ __forceinline__ int node_visit_q(const TreeView &T, const EvalArgs &A
         // accurate as the far-field box distance can be here
         float D = fsqrt(D2);
         float inv = frcp(D);
-        const double L = fma(-A.alpha64, (double)D, (double)logn + T.slogA);
+        const double L = fma(-A.alpha64, (double)D, fma((double)max(pay, 0), 1.0 / (1 << kLogFracBits), T.slogA));
         lse_add<GRAD>(st, L, D * kLo, dx * inv, dy * inv, dz * inv);
     }
     return slot;

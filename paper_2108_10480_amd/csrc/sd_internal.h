@@ -7,6 +7,11 @@
 #include "../../include/sd.h"
 
 namespace sd {
+// fractional bits of the fixed-point log n_B in a node's payload
+constexpr int kLogFracBits = 26;
+}  // namespace sd
+
+namespace sd {
 
 // ---------------------------------------------------------------------------
 // Error plumbing: every ABI entry point returns a code and records a message.
@@ -75,7 +80,8 @@ class AsyncScratch {
 //
 //   node_lo[i] = (min.x, min.y, min.z, bits: escape index, -1 = end)
 //   node_hi[i] = (max.x, max.y, max.z, payload)
-//   payload: internal node -> float log(n_B), round to nearest (n_B = leaves below);
+//   payload: internal node -> int log(n_B) * 2^kLogFracBits, rounded to nearest
+//            (n_B = leaves below; non-negative);
 //            leaf           -> int bits 0x80000000 | leaf slot.
 //   The left child of internal node i is i + 1; its right child is the left
 //   child's escape index.
