@@ -551,6 +551,19 @@ __device__ __forceinline__ void load_node(const TreeView &T, int node, float4 &l
     hi = *reinterpret_cast<const float4 *>(base + off + 16);
 }
 
+// The query in FP64 for the far-field terms' exact differences q - y_B.  The
+// traversal loops form it once and pin it in registers (an empty asm that
+// takes and returns it), since the compiler would otherwise convert the query
+// again for every far-field term.
+struct Q64 {
+    double x, y, z;
+};
+__device__ __forceinline__ Q64 q64_pinned(float qx, float qy, float qz) {
+    Q64 q{(double)qx, (double)qy, (double)qz};
+    asm volatile("" : "+v"(q.x), "+v"(q.y), "+v"(q.z));
+    return q;
+}
+
 // One step of Alg. 1 on `node`, whose record (lo, hi) is in registers: the
 // opening test, then the next node (escape after a far-field term or a leaf,
 // else the left child node + 1), whose record is loaded into (lo, hi) before
@@ -558,8 +571,8 @@ __device__ __forceinline__ void load_node(const TreeView &T, int node, float4 &l
 // Returns the leaf slot to evaluate, or -1.
 template <bool GRAD, bool COUNT, bool PRUNE, class St>
 __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, float qx, float qy,
-                                          float qz, St &st, float4 &lo, float4 &hi, int &node,
-                                          float4 &leaf_lo, int &n_vis, int &n_far) {
+                                          float qz, const Q64 &qd, St &st, float4 &lo, float4 &hi,
+                                          int &node, float4 &leaf_lo, int &n_vis, int &n_far) {
     const float yx = clampf(qx, lo.x, hi.x);
     const float yy = clampf(qy, lo.y, hi.y);
     const float yz = clampf(qz, lo.z, hi.z);
@@ -598,7 +611,7 @@ __device__ __forceinline__ int node_visit(const TreeView &T, const EvalArgs &A, 
         // distance in FP64 from the exact differences q - y_B.
         const float D = fsqrt(D2);
         const float inv = frcp(D);
-        const double ux = (double)qx - (double)yx, uy = (double)qy - (double)yy, uz = (double)qz - (double)yz;
+        const double ux = qd.x - (double)yx, uy = qd.y - (double)yy, uz = qd.z - (double)yz;
         const double D64 = sqrt_newton_pos(ddot3(ux, uy, uz, ux, uy, uz), D, inv);
         // log n_B from the payload's fixed point (a leaf's negative payload
         // gives log 1 = 0)
@@ -713,10 +726,11 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
     if (CLS == 0 || A.defer == 0) {
         // leaves inline; the loop condition is a wave-uniform mask (see below)
         if (__builtin_amdgcn_sicmp(node, 0, 39 /* >= */) != 0) {
+            const Q64 qd = q64_pinned(qx, qy, qz);
             do {
                 if (node >= 0) {
-                    int slot = node_visit<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, lo, hi, node, leaf_lo,
-                                                              n_vis, n_far);
+                    int slot = node_visit<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, qd, st, lo, hi, node,
+                                                              leaf_lo, n_vis, n_far);
                     if (slot >= 0) {
                         if (COUNT) ++n_leaf;
                         Term t = leaf_term<CLS, GRAD>(T, A, slot, leaf_lo, qx, qy, qz, metric);
@@ -747,10 +761,11 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
         uint64_t room = __builtin_amdgcn_sicmp(cnt, kQ, 40 /* < */);
         bool go = ((live & room) != 0) & ((live & ~room) == 0);
         if (go) {
+            const Q64 qd = q64_pinned(qx, qy, qz);
             do {
                 if (node >= 0 && cnt < kQ) {
-                    int slot = node_visit<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, st, lo, hi, node, leaf_lo,
-                                                              n_vis, n_far);
+                    int slot = node_visit<GRAD, COUNT, PRUNE>(T, A, qx, qy, qz, qd, st, lo, hi, node,
+                                                              leaf_lo, n_vis, n_far);
                     if (slot >= 0) {
                         lq.slot[cnt][lane] = slot;
                         ++cnt;
