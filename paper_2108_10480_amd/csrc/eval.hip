@@ -1429,9 +1429,9 @@ k_query_keys(const float *__restrict__ Q, const uint32_t *__restrict__ idx, int6
 // and the fourth wave's latency hiding is worth about 10 % (the few spills of
 // the triangle-on-triangle variants included).
 template <int NV, int MASK>
-__global__ void __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(kEB) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_evalq(EvalArgs A, const float *__restrict__ G) {
-    int i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * kEB + threadIdx.x;
     if (i >= A.nthr) return;
     int qi = A.perm ? (int)A.perm[i] : i;
     if ((unsigned)qi >= (unsigned)A.nq) return;
@@ -1450,7 +1450,7 @@ k_evalq(EvalArgs A, const float *__restrict__ G) {
         g.mn[1] = fminf(g.mn[1], g.v[v].y); g.mx[1] = fmaxf(g.mx[1], g.v[v].y);
         g.mn[2] = fminf(g.mn[2], g.v[v].z); g.mx[2] = fmaxf(g.mx[2], g.v[v].z);
     }
-    __shared__ LeafQueue lqs[(MASK & 6) ? kB / 64 : 1];
+    __shared__ LeafQueue lqs[(MASK & 6) ? kEB / 64 : 1];
     LeafQueue &lq = lqs[(MASK & 6) ? threadIdx.x / 64 : 0];
     LSE st;
     lse_init(st);
@@ -1471,10 +1471,11 @@ k_centroids(const float *__restrict__ G, int nv, int64_t n, float *__restrict__ 
 }
 
 template <int NV>
-void launch_evalq(const EvalArgs &A, const float *G, int mask, unsigned grid, hipStream_t s) {
+void launch_evalq(const EvalArgs &A, const float *G, int mask, hipStream_t s) {
+    const unsigned grid = (unsigned)(((int64_t)A.nthr + kEB - 1) / kEB);
     switch (mask & 7) {
 #define SD_CASE(m) \
-    case m: hipLaunchKernelGGL((k_evalq<NV, m>), dim3(grid), dim3(kB), 0, s, A, G); break;
+    case m: hipLaunchKernelGGL((k_evalq<NV, m>), dim3(grid), dim3(kEB), 0, s, A, G); break;
         SD_CASE(1) SD_CASE(2) SD_CASE(3) SD_CASE(4) SD_CASE(5) SD_CASE(6) SD_CASE(7)
 #undef SD_CASE
         default: break;
@@ -1490,12 +1491,12 @@ struct TraceArgs {
 };
 
 template <int MASK>
-__global__ void __launch_bounds__(kB) k_trace(EvalArgs A, TraceArgs R) {
-    const int i = blockIdx.x * kB + threadIdx.x;
+__global__ void __launch_bounds__(kEB) k_trace(EvalArgs A, TraceArgs R) {
+    const int i = blockIdx.x * kEB + threadIdx.x;
     if (i >= A.nq) return;
     const float ox = R.O[3 * (int64_t)i], oy = R.O[3 * (int64_t)i + 1], oz = R.O[3 * (int64_t)i + 2];
     const float ux = R.U[3 * (int64_t)i], uy = R.U[3 * (int64_t)i + 1], uz = R.U[3 * (int64_t)i + 2];
-    __shared__ LeafQueue lqs[(MASK & 6) ? kB / 64 : 1];
+    __shared__ LeafQueue lqs[(MASK & 6) ? kEB / 64 : 1];
     LeafQueue &lq = lqs[(MASK & 6) ? threadIdx.x / 64 : 0];
     float t = 0.f, t_hit = INFINITY;
     int steps = 0;
@@ -1522,10 +1523,11 @@ __global__ void __launch_bounds__(kB) k_trace(EvalArgs A, TraceArgs R) {
     if (R.steps_out) R.steps_out[i] = steps;
 }
 
-void launch_trace(const EvalArgs &A, const TraceArgs &R, int mask, unsigned grid, hipStream_t s) {
+void launch_trace(const EvalArgs &A, const TraceArgs &R, int mask, hipStream_t s) {
+    const unsigned grid = (unsigned)(((int64_t)A.nq + kEB - 1) / kEB);
     switch (mask & 7) {
 #define SD_CASE(m) \
-    case m: hipLaunchKernelGGL((k_trace<m>), dim3(grid), dim3(kB), 0, s, A, R); break;
+    case m: hipLaunchKernelGGL((k_trace<m>), dim3(grid), dim3(kEB), 0, s, A, R); break;
         SD_CASE(1) SD_CASE(2) SD_CASE(3) SD_CASE(4) SD_CASE(5) SD_CASE(6) SD_CASE(7)
 #undef SD_CASE
         default: break;
@@ -1812,8 +1814,8 @@ int evalq_dispatch(const sd_scene *sc, const float *G, int nv, int64_t n, const 
         SD_TRY(query_order(sc, cen, n, perm, s));
         A.perm = perm;
     }
-    if (nv == 2) launch_evalq<2>(A, G, mask, grid, s);
-    else launch_evalq<3>(A, G, mask, grid, s);
+    if (nv == 2) launch_evalq<2>(A, G, mask, s);
+    else launch_evalq<3>(A, G, mask, s);
     SD_HIP(hipGetLastError());
     return SD_OK;
 }
@@ -1837,7 +1839,7 @@ int trace_dispatch(const sd_scene *sc, const float *O, const float *U, int64_t n
         return SD_OK;
     }
     TraceArgs R{O, U, level, eps, t_max, max_steps, t_out, steps_out};
-    launch_trace(A, R, mask, grid, s);
+    launch_trace(A, R, mask, s);
     SD_HIP(hipGetLastError());
     return SD_OK;
 }
