@@ -224,38 +224,72 @@ k_karras(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ lef
     if (i == 0) parent[0] = -1;
 }
 
-__global__ void __launch_bounds__(kB)
-k_refit(const float4 *__restrict__ plo, const float4 *__restrict__ phi,
-        const uint32_t *__restrict__ order, int64_t n, const int32_t *__restrict__ left,
-        const int32_t *__restrict__ right, const int32_t *__restrict__ parent,
-        const int32_t *__restrict__ first, const int32_t *__restrict__ last,
-        uint32_t *__restrict__ flag, float4 *nlo, float4 *nhi) {
-    int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x;
+// Bottom-up refit in two launches.  A node's box is formed by the second of
+// its two children to finish (a counter per node orders the two), from the
+// children's boxes.  The release/acquire that orders one thread's box write
+// before another's read is cheap inside a workgroup, but between workgroups,
+// which may run on different XCDs with separate L2 caches, it writes back and
+// invalidates the whole L2 on every node.  So the first launch refits only the
+// nodes whose leaves all belong to one workgroup (kRB consecutive leaves);
+// a finished child whose parent spans several workgroups is appended to a
+// list instead.  The second launch, a single workgroup, refits the nodes above
+// from that list (the first launch's boxes are visible after the launch
+// boundary, and its own threads synchronise at workgroup scope).
+constexpr int kRB = 1024;
+
+__device__ __forceinline__ void refit_node(int32_t cur, const int32_t *__restrict__ left,
+                                           const int32_t *__restrict__ right, float4 *nlo, float4 *nhi) {
+    const float4 al = nlo[left[cur]], ah = nhi[left[cur]];
+    const float4 bl = nlo[right[cur]], bh = nhi[right[cur]];
+    nlo[cur] = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.f);
+    nhi[cur] = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.f);
+}
+
+__global__ void __launch_bounds__(kRB)
+k_refit_local(const float4 *__restrict__ plo, const float4 *__restrict__ phi,
+              const uint32_t *__restrict__ order, int64_t n, const int32_t *__restrict__ left,
+              const int32_t *__restrict__ right, const int32_t *__restrict__ parent,
+              const int32_t *__restrict__ first, const int32_t *__restrict__ last,
+              uint32_t *__restrict__ flag, float4 *nlo, float4 *nhi, int32_t *__restrict__ ready,
+              uint32_t *__restrict__ n_ready) {
+    const int64_t k = (int64_t)blockIdx.x * kRB + threadIdx.x;
     if (k >= n) return;
-    // leaves [wlo, whi] belong to this workgroup: a node whose leaf range lies
-    // inside it is reached only by this workgroup's threads, so its counter
-    // orders their box writes at workgroup scope; nodes spanning several
-    // workgroups need agent scope (the L2 write-back and invalidation that
-    // makes the boxes visible across XCDs)
-    const int64_t wlo = (int64_t)blockIdx.x * kB, whi = wlo + kB - 1;
-    int64_t node = n - 1 + k;
-    uint32_t p = order[k];
+    // leaves [wlo, whi] belong to this workgroup
+    const int64_t wlo = (int64_t)blockIdx.x * kRB, whi = wlo + kRB - 1;
+    int32_t node = (int32_t)(n - 1 + k);
+    const uint32_t p = order[k];
     nlo[node] = plo[p];
     nhi[node] = phi[p];
-    if (n == 1) return;
+    if (n == 1) return;   // the leaf is the root (no parent links are built)
     int32_t cur = parent[node];
     while (cur >= 0) {
-        const bool local = first[cur] >= wlo && last[cur] <= whi;
-        uint32_t old = local ? __hip_atomic_fetch_add(&flag[cur], 1u, __ATOMIC_ACQ_REL,
-                                                      __HIP_MEMORY_SCOPE_WORKGROUP)
-                             : __hip_atomic_fetch_add(&flag[cur], 1u, __ATOMIC_ACQ_REL,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
+        if (first[cur] < wlo || last[cur] > whi) {
+            // the parent spans several workgroups: left to the second launch
+            const uint32_t slot = __hip_atomic_fetch_add(n_ready, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ready[slot] = node;
+            return;
+        }
+        const uint32_t old = __hip_atomic_fetch_add(&flag[cur], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (old == 0) return;   // the sibling subtree is not finished yet
-        float4 al = nlo[left[cur]], ah = nhi[left[cur]];
-        float4 bl = nlo[right[cur]], bh = nhi[right[cur]];
-        nlo[cur] = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.f);
-        nhi[cur] = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.f);
-        cur = parent[cur];   // the next acq_rel counter update releases this box
+        refit_node(cur, left, right, nlo, nhi);
+        node = cur;
+        cur = parent[cur];   // the next counter update releases this box
+    }
+}
+
+__global__ void __launch_bounds__(kRB)
+k_refit_upper(const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+              const int32_t *__restrict__ parent, uint32_t *__restrict__ flag, float4 *nlo, float4 *nhi,
+              const int32_t *__restrict__ ready, const uint32_t *__restrict__ n_ready) {
+    const uint32_t m = *n_ready;
+    for (uint32_t e = threadIdx.x; e < m; e += kRB) {
+        int32_t cur = parent[ready[e]];
+        while (cur >= 0) {
+            const uint32_t old = __hip_atomic_fetch_add(&flag[cur], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;
+            refit_node(cur, left, right, nlo, nhi);
+            cur = parent[cur];
+        }
     }
 }
 
@@ -468,7 +502,10 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
     SD_TRY(tmp.alloc(&blo, nn)); SD_TRY(tmp.alloc(&bhi, nn));
     SD_TRY(tmp.alloc(&keys, n)); SD_TRY(tmp.alloc(&keys2, n));
     SD_TRY(tmp.alloc(&vals, n)); SD_TRY(tmp.alloc(&vals2, n));
-    SD_TRY(tmp.alloc(&flag, nn));
+    SD_TRY(tmp.alloc(&flag, nn + 1));
+    uint32_t *n_ready = flag + nn;   // the count of the refit's list, cleared with the counters
+    int32_t *ready;                  // a node has two children: at most 2 (n - 1) entries
+    SD_TRY(tmp.alloc(&ready, std::max<int64_t>(1, 2 * (n - 1))));
     SD_TRY(tmp.alloc(&left, nn)); SD_TRY(tmp.alloc(&right, nn));
     SD_TRY(tmp.alloc(&first, nn)); SD_TRY(tmp.alloc(&last, nn)); SD_TRY(tmp.alloc(&parent, nn));
     SD_TRY(tmp.alloc(&temp, (int64_t)tb));
@@ -485,12 +522,14 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
                        red_dev);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n)), dim3(kB), 0, s, plo, phi, n, red_dev, keys, vals);
     SD_TRY(radix_sort_pairs(keys, vals, keys2, vals2, n, 63, temp, s));
-    SD_HIP(hipMemsetAsync(flag, 0, nn * sizeof(uint32_t), s));
+    SD_HIP(hipMemsetAsync(flag, 0, (nn + 1) * sizeof(uint32_t), s));
     if (n > 1)
         hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1)), dim3(kB), 0, s, keys, n, left, right,
                            first, last, parent);
-    hipLaunchKernelGGL(k_refit, dim3(grid_for(n)), dim3(kB), 0, s, plo, phi, vals, n, left, right,
-                       parent, first, last, flag, blo, bhi);
+    hipLaunchKernelGGL(k_refit_local, dim3((unsigned)((n + kRB - 1) / kRB)), dim3(kRB), 0, s, plo, phi, vals,
+                       n, left, right, parent, first, last, flag, blo, bhi, ready, n_ready);
+    hipLaunchKernelGGL(k_refit_upper, dim3(1), dim3(kRB), 0, s, left, right, parent, flag, blo, bhi, ready,
+                       n_ready);
     int64_t acc = 0;
     SD_TRY(dalloc(&sc->lo[cls], 2 * nn, s, &acc));
     sc->hi[cls] = sc->lo[cls] + 1;
