@@ -426,52 +426,48 @@ __device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float 
     const double det = g11 * g22 - g12 * g12;
 
     // region: 0 face, 1 edge ab, 2 edge ac, 3 edge bc, 4 vertex; the edge and
-    // face coordinates are num / den, formed after the branches
-    int region;
-    double p1 = 0.0, p2 = 0.0, num = 0.0, num2 = 0.0, den = 1.0, inv_den = 0.0;
+    // face coordinates are num / den.  Every test is formed and the first that
+    // holds, in Ericson's order (vertex a, vertex b, edge ab, vertex c, edge
+    // ac, edge bc, else the face), is selected without branches: the 64
+    // (query, triangle) pairs a wave evaluates together fall in different
+    // regions, and branches would run most of the paths anyway.
+    const double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
+    const double e43 = d4 - d3, e56 = d5 - d6;
+    const bool in_a = d1 <= 0.0 && d2 <= 0.0;
+    const bool in_b = d3 >= 0.0 && d4 <= d3;
+    const bool in_ab = vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0;
+    const bool in_c = d6 >= 0.0 && d5 <= d6;
+    const bool in_ac = vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0;
+    const bool in_bc = va <= 0.0 && e43 >= 0.0 && e56 >= 0.0;
+    int region = 0;
+    double num = vb, num2 = vc, den = va + vb + vc;
+    if (in_bc) { region = 3; num = e43; den = e43 + e56; }
+    if (in_ac) { region = 2; num = d2; den = d2 - d6; }
+    if (in_c) region = 4;
+    if (in_ab) { region = 1; num = d1; den = d1 - d3; }
+    if (in_b || in_a) region = 4;
+    double p1 = (in_b && !in_a) ? 1.0 : 0.0;
+    double p2 = (in_c && !(in_a || in_b || in_ab)) ? 1.0 : 0.0;
     if (!(nn > 0.0 && det > 0.0)) {
         // zero-area triangle: it is its longest edge (which covers the other
         // two), first of ab, bc, ca on ties, so the barycentrics are unique
         const double bcx = acx - abx, bcy = acy - aby, bcz = acz - abz;   // exact: v2 - v1
         const double lbc = ddot3(bcx, bcy, bcz, bcx, bcy, bcz);
+        p1 = p2 = 0.0;
         if (g11 >= lbc && g11 >= g22) {
             region = 1; num = d1; den = g11;                       // t along ab
         } else if (lbc >= g22) {
-            region = 3; num = (d4 - d3); den = lbc;                // t along bc
+            region = 3; num = e43; den = lbc;                      // t along bc
         } else {
             region = 2; num = d2; den = g22;                       // t along ac
         }
-    } else if (d1 <= 0.0 && d2 <= 0.0) {
-        region = 4;
-    } else if (d3 >= 0.0 && d4 <= d3) {
-        region = 4; p1 = 1.0;
-    } else {
-        const double vc = d1 * d4 - d3 * d2;
-        if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
-            region = 1; num = d1; den = d1 - d3;
-        } else if (d6 >= 0.0 && d5 <= d6) {
-            region = 4; p2 = 1.0;
-        } else {
-            const double vb = d5 * d2 - d1 * d6;
-            if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
-                region = 2; num = d2; den = d2 - d6;
-            } else {
-                const double va = d3 * d6 - d5 * d4;
-                if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
-                    region = 3; num = d4 - d3; den = (d4 - d3) + (d5 - d6);
-                } else {
-                    region = 0; num = vb; num2 = vc; den = va + vb + vc;
-                }
-            }
-        }
     }
+    double inv_den = 0.0;
     if (region != 4) {
         inv_den = den > 0.0 ? 1.0 / den : 0.0;
         const double t = fmin(fmax(num * inv_den, 0.0), 1.0);   // degenerate edges clamp here
-        if (region == 0) { p1 = num * inv_den; p2 = num2 * inv_den; }
-        else if (region == 1) { p1 = t; }
-        else if (region == 2) { p2 = t; }
-        else { p1 = 1.0 - t; p2 = t; }
+        p1 = region == 0 ? num * inv_den : (region == 1 ? t : (region == 3 ? 1.0 - t : 0.0));
+        p2 = region == 0 ? num2 * inv_den : ((region == 2 || region == 3) ? t : 0.0);
         if (!(nn > 0.0 && det > 0.0) && !(t > 0.0 && t < 1.0)) region = 4;
     }
     const double cx = fma(-p2, acx, fma(-p1, abx, apx)), cy = fma(-p2, acy, fma(-p1, aby, apy)),
@@ -493,25 +489,17 @@ __device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float 
         float k = S * frcp((float)w.w) * inv_alpha;
         if (metric) k *= inv_alpha;
         // grad w~ (Eq. 5) in FP64: the barycentric gradients are large (1 / the
-        // triangle's altitude) and their combination cancels
-        double wgx = 0.0, wgy = 0.0, wgz = 0.0;
-        if (region == 0) {
-            // grad phi1 = (g22 ab - g12 ac) / det, grad phi2 = (g11 ac - g12 ab) / det
-            // (va + vb + vc = det is the face region's denominator)
-            const double c1 = (w.wx * g22 - w.wy * g12) * inv_den, c2 = (w.wy * g11 - w.wx * g12) * inv_den;
-            wgx = fma(c1, abx, c2 * acx);
-            wgy = fma(c1, aby, c2 * acy);
-            wgz = fma(c1, abz, c2 * acz);
-        } else if (region != 4) {
-            // along the edge e: d t / dq = e / |e|^2 for the edge's parameter t
-            // (the edge regions' denominator den is |e|^2)
-            double ex, ey, ez, dwdt;
-            if (region == 1) { ex = abx; ey = aby; ez = abz; dwdt = w.wx; }
-            else if (region == 2) { ex = acx; ey = acy; ez = acz; dwdt = w.wy; }
-            else { ex = acx - abx; ey = acy - aby; ez = acz - abz; dwdt = w.wy - w.wx; }
-            const double c = dwdt * inv_den;
-            wgx = c * ex; wgy = c * ey; wgz = c * ez;
-        }
+        // triangle's altitude) and their combination cancels.  grad w~ =
+        // c1 ab + c2 ac in every region.  Face: grad phi1 = (g22 ab - g12 ac) /
+        // det, grad phi2 = (g11 ac - g12 ab) / det (va + vb + vc = det is the
+        // face region's denominator).  Edge e with parameter t: d t / dq = e /
+        // |e|^2 (the edge regions' denominator den is |e|^2), and bc = ac - ab.
+        // Vertex: 0 (inv_den = 0 there as well).
+        const double cf1 = (w.wx * g22 - w.wy * g12) * inv_den, cf2 = (w.wy * g11 - w.wx * g12) * inv_den;
+        const double cbc = (w.wy - w.wx) * inv_den;
+        const double c1 = region == 0 ? cf1 : (region == 1 ? w.wx * inv_den : (region == 3 ? -cbc : 0.0));
+        const double c2 = region == 0 ? cf2 : (region == 2 ? w.wy * inv_den : (region == 3 ? cbc : 0.0));
+        const double wgx = fma(c1, abx, c2 * acx), wgy = fma(c1, aby, c2 * acy), wgz = fma(c1, abz, c2 * acz);
         o.gx = fmaf(-k, (float)wgx, gx);
         o.gy = fmaf(-k, (float)wgy, gy);
         o.gz = fmaf(-k, (float)wgz, gz);
