@@ -69,20 +69,20 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     return x;
 }
 
-// Primitive boxes, plus the scene-wide bounds, reduced over each workgroup
-// (lane shuffles, then the four wave results through LDS) so that one thread
-// per workgroup updates the shared record: its 13 words share one cache line,
-// whose atomics the L2 serialises.  Lanes past the end take part in the
-// reductions with neutral values.
+// Primitive boxes, plus the scene-wide bounds: each thread reduces the
+// primitives of its grid-stride loop, then each workgroup (lane shuffles, then
+// the four wave results through LDS), so that one thread per workgroup
+// updates the shared record.  Its 13 words share one cache line, whose atomics
+// the L2 serialises, so the grid is capped (kBoxBlocks workgroups) rather than
+// one workgroup per 256 primitives.
+constexpr unsigned kBoxBlocks = 1024;
 template <int K>
 __global__ void __launch_bounds__(kB)
 k_prim_boxes(const float *__restrict__ V, int64_t nV, const int32_t *__restrict__ ids, int64_t n,
              float4 *__restrict__ blo, float4 *__restrict__ bhi, Reduce *red) {
-    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    const bool live = i < n;
     uint32_t cmn[3], cmx[3], bmn[3], bmx[3], dmx = 0u;
     for (int a = 0; a < 3; ++a) { cmn[a] = bmn[a] = 0xffffffffu; cmx[a] = bmx[a] = 0u; }
-    if (live) {
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
         int id[3];
         load_ids<K>(ids, i, nV, id, &red->bad);
         float lo[3], hi[3];
@@ -97,14 +97,15 @@ k_prim_boxes(const float *__restrict__ V, int64_t nV, const int32_t *__restrict_
         bhi[i] = make_float4(hi[0], hi[1], hi[2], 0.f);
         float dd = 0.f;
         for (int a = 0; a < 3; ++a) {
-            float c = 0.5f * (lo[a] + hi[a]);
-            cmn[a] = cmx[a] = f2o(c);
-            bmn[a] = f2o(lo[a]);
-            bmx[a] = f2o(hi[a]);
+            const uint32_t c = f2o(0.5f * (lo[a] + hi[a]));
+            cmn[a] = min(cmn[a], c);
+            cmx[a] = max(cmx[a], c);
+            bmn[a] = min(bmn[a], f2o(lo[a]));
+            bmx[a] = max(bmx[a], f2o(hi[a]));
             float e = hi[a] - lo[a];
             dd = fmaf(e, e, dd);
         }
-        dmx = f2o(sqrtf(dd));
+        dmx = max(dmx, f2o(sqrtf(dd)));
     }
     for (int a = 0; a < 3; ++a) {
         cmn[a] = wave_min_u32(cmn[a]);
@@ -230,12 +231,15 @@ k_karras(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ lef
 // before another's read is cheap inside a workgroup, but between workgroups,
 // which may run on different XCDs with separate L2 caches, it writes back and
 // invalidates the whole L2 on every node.  So the first launch refits only the
-// nodes whose leaves all belong to one workgroup (kRB consecutive leaves);
-// a finished child whose parent spans several workgroups is appended to a
-// list instead.  The second launch, a single workgroup, refits the nodes above
-// from that list (the first launch's boxes are visible after the launch
-// boundary, and its own threads synchronise at workgroup scope).
+// nodes whose leaves all belong to one workgroup's unit of kRU consecutive
+// leaves (each thread takes kRU / kRB of them in turn); a finished child whose
+// parent spans several units is appended to a list instead.  The second
+// launch, a single workgroup, refits the nodes above from that list (the
+// first launch's boxes are visible after the launch boundary, and its own
+// threads synchronise at workgroup scope).  Large units keep that list short:
+// about 4 n / kRU entries.
 constexpr int kRB = 1024;
+constexpr int64_t kRU = 16 * kRB;
 
 __device__ __forceinline__ void refit_node(int32_t cur, const int32_t *__restrict__ left,
                                            const int32_t *__restrict__ right, float4 *nlo, float4 *nhi) {
@@ -252,28 +256,28 @@ k_refit_local(const float4 *__restrict__ plo, const float4 *__restrict__ phi,
               const int32_t *__restrict__ first, const int32_t *__restrict__ last,
               uint32_t *__restrict__ flag, float4 *nlo, float4 *nhi, int32_t *__restrict__ ready,
               uint32_t *__restrict__ n_ready) {
-    const int64_t k = (int64_t)blockIdx.x * kRB + threadIdx.x;
-    if (k >= n) return;
     // leaves [wlo, whi] belong to this workgroup
-    const int64_t wlo = (int64_t)blockIdx.x * kRB, whi = wlo + kRB - 1;
-    int32_t node = (int32_t)(n - 1 + k);
-    const uint32_t p = order[k];
-    nlo[node] = plo[p];
-    nhi[node] = phi[p];
-    if (n == 1) return;   // the leaf is the root (no parent links are built)
-    int32_t cur = parent[node];
-    while (cur >= 0) {
-        if (first[cur] < wlo || last[cur] > whi) {
-            // the parent spans several workgroups: left to the second launch
-            const uint32_t slot = __hip_atomic_fetch_add(n_ready, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ready[slot] = node;
-            return;
+    const int64_t wlo = (int64_t)blockIdx.x * kRU, whi = wlo + kRU - 1;
+    for (int64_t k = wlo + threadIdx.x; k <= whi && k < n; k += kRB) {
+        int32_t node = (int32_t)(n - 1 + k);
+        const uint32_t p = order[k];
+        nlo[node] = plo[p];
+        nhi[node] = phi[p];
+        if (n == 1) return;   // the leaf is the root (no parent links are built)
+        int32_t cur = parent[node];
+        while (cur >= 0) {
+            if (first[cur] < wlo || last[cur] > whi) {
+                // the parent spans several units: left to the second launch
+                const uint32_t slot = __hip_atomic_fetch_add(n_ready, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ready[slot] = node;
+                break;
+            }
+            const uint32_t old = __hip_atomic_fetch_add(&flag[cur], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;   // the sibling subtree is not finished yet
+            refit_node(cur, left, right, nlo, nhi);
+            node = cur;
+            cur = parent[cur];   // the next counter update releases this box
         }
-        const uint32_t old = __hip_atomic_fetch_add(&flag[cur], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (old == 0) return;   // the sibling subtree is not finished yet
-        refit_node(cur, left, right, nlo, nhi);
-        node = cur;
-        cur = parent[cur];   // the next counter update releases this box
     }
 }
 
@@ -518,7 +522,7 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
     }
     init.diam = 0; init.bad = red_host->bad; init.maxv = red_host->maxv; init.pad = 0;
     SD_HIP(hipMemcpyAsync(red_dev, &init, sizeof(Reduce), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_prim_boxes<K>, dim3(grid_for(n)), dim3(kB), 0, s, V, nV, ids, n, plo, phi,
+    hipLaunchKernelGGL(k_prim_boxes<K>, dim3(std::min(grid_for(n), kBoxBlocks)), dim3(kB), 0, s, V, nV, ids, n, plo, phi,
                        red_dev);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n)), dim3(kB), 0, s, plo, phi, n, red_dev, keys, vals);
     SD_TRY(radix_sort_pairs(keys, vals, keys2, vals2, n, 63, temp, s));
@@ -526,7 +530,7 @@ static int build_class(sd_scene *sc, int cls, const float *V, int64_t nV, const 
     if (n > 1)
         hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1)), dim3(kB), 0, s, keys, n, left, right,
                            first, last, parent);
-    hipLaunchKernelGGL(k_refit_local, dim3((unsigned)((n + kRB - 1) / kRB)), dim3(kRB), 0, s, plo, phi, vals,
+    hipLaunchKernelGGL(k_refit_local, dim3((unsigned)((n + kRU - 1) / kRU)), dim3(kRB), 0, s, plo, phi, vals,
                        n, left, right, parent, first, last, flag, blo, bhi, ready, n_ready);
     hipLaunchKernelGGL(k_refit_upper, dim3(1), dim3(kRB), 0, s, left, right, parent, flag, blo, bhi, ready,
                        n_ready);
