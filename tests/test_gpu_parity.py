@@ -412,3 +412,27 @@ def test_alpha_sweep_terrain_both_precision_modes(alpha):
         d, g = d.cpu().numpy(), g.cpu().numpy()
         compare(d, g, dr, gr, floor_of(sc), what=f"alpha {alpha} flags {fl}", dmin=dm)
         _check_conservative(scene, Q, alpha, 0.5, dm, d, flags=fl)
+
+
+@pytest.mark.parametrize("nq", [1, 63, 64, 65, 4095, 4096, 4097])
+def test_query_counts_around_the_wave_and_the_sort_threshold(nq):
+    """The traversal is launched one wave (64 queries) per workgroup and sorts
+    its queries by Morton code from 4,096 on: counts on both sides of each
+    boundary, on the mixed three-class scene, against the oracle element by
+    element, with value-only and value+gradient calls agreeing bit for bit."""
+    require_gpu()
+    sc = _mixed_scene()
+    scene = api.upload_scene(sc)
+    try:
+        Q = _queries(sc, nq, seed=nq)
+        d, g = _run(scene, Q, 50.0, 0.5)
+        dv = api.sd_eval(scene, cuda(Q), 50.0, 0.5)
+        torch.cuda.synchronize()
+        assert np.array_equal(dv.cpu().numpy(), d)
+        osc = oracle_scene(sc)
+        dr, gr, _ = O.barnes_hut(osc, oracle_trees(scene), Q.astype(np.float64), 50.0, 0.5, cut_f32=True)
+        dm = O.dmin(osc, Q.astype(np.float64))
+        compare(d, g, dr, gr, floor_of(sc), what=f"mixed nq={nq}", dmin=dm)
+        _check_conservative(scene, Q, 50.0, 0.5, dm, d)
+    finally:
+        scene.free()
