@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4_000_000,
                     help="queries of the headline workload timed on the FP64 oracle and checked against it")
     ap.add_argument("--headline-only", action="store_true", help="only the headline workload (for profiling)")
+    ap.add_argument("--icosphere-only", type=float, default=None, metavar="ALPHA",
+                    help="only the icosphere workload at this alpha (for profiling); prints its record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate comparison")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid-body street workload")
@@ -249,6 +251,11 @@ def main():
     from paper_2108_10480_amd import api, scenes
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.icosphere_only is not None:
+        res, _, scene = icosphere_leg(args, np, torch, api, scenes, alphas=(args.icosphere_only,))
+        scene.free()
+        print(json.dumps(res))
+        return
     dev = torch.device("cuda:0")
     _progress("terrain scene and queries")
     sc = scenes.terrain_scene(args.scale)
@@ -453,7 +460,7 @@ def point_sphere_leg(args, np, torch, api, scenes):
     return res
 
 
-def icosphere_leg(args, np, torch, api, scenes):
+def icosphere_leg(args, np, torch, api, scenes, alphas=ICO_ALPHAS):
     """The bumpy level-7 icosphere (327,680 triangles) with 1M queries (half
     uniform in [-1.5, 1.5]^3, half within 0.02 of the surface) at alpha 50
     and 500: throughput, work, roofline fraction, and a 200,000-query sample
@@ -482,7 +489,7 @@ def icosphere_leg(args, np, torch, api, scenes):
         floor = 1e-3 * float(np.linalg.norm(hi - lo))
         idx = np.sort(np.random.default_rng(789).choice(n, size=200_000, replace=False))
         idx_d = torch.as_tensor(idx, device="cuda")
-    for alpha in ICO_ALPHAS:
+    for alpha in alphas:
         ms, order_ms, trav = _timed_steps(torch, _ordered_step(api, scene, Qd, perm, d, g, alpha, args.beta), 20, 3)
         c = api.sd_eval_counters(scene, Qd, alpha, args.beta, flags=api.SD_COUNTERS_BY_CLASS).cpu().numpy()
         work, flops_q, bytes_q = _work(np, c)
