@@ -237,7 +237,8 @@ k_karras(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ lef
 // launch, a single workgroup, refits the nodes above from that list (the
 // first launch's boxes are visible after the launch boundary, and its own
 // threads synchronise at workgroup scope).  Large units keep that list short:
-// about 4 n / kRU entries.
+// it holds the finished children of the nodes that span units, which are
+// few per unit.
 constexpr int kRB = 1024;
 constexpr int64_t kRU = 16 * kRB;
 
