@@ -345,8 +345,8 @@ struct Term {
     float lw, dlo, gx, gy, gz;
 };
 
-template <bool GRAD>
-__device__ __forceinline__ Term point_term(float4 p, float qx, float qy, float qz) {
+template <bool GRAD, class QT>
+__device__ __forceinline__ Term point_term(float4 p, QT qx, QT qy, QT qz) {
     const double ex = (double)qx - (double)p.x, ey = (double)qy - (double)p.y, ez = (double)qz - (double)p.z;
     const double s = ddot3(ex, ey, ez, ex, ey, ez);
     const float r = fsqrt((float)s);
@@ -363,8 +363,8 @@ __device__ __forceinline__ Term point_term(float4 p, float qx, float qy, float q
 }
 
 // segment v0 -> v1 with end weights a = 1/|N_0|, b = 1/|N_1| (App. C.2 quartic)
-template <bool GRAD>
-__device__ __forceinline__ Term edge_term(float4 r0, float4 r1, float qx, float qy, float qz,
+template <bool GRAD, class QT>
+__device__ __forceinline__ Term edge_term(float4 r0, float4 r1, QT qx, QT qy, QT qz,
                                           float S, float slogA, float inv_alpha, bool metric) {
     const double ex = (double)r1.x - (double)r0.x, ey = (double)r1.y - (double)r0.y,
                  ez = (double)r1.z - (double)r0.z;
@@ -406,9 +406,9 @@ __device__ __forceinline__ Term edge_term(float4 r0, float4 r1, float qx, float 
 // Region classification after Ericson (Real-Time Collision Detection, 5.1.5)
 // in FP64 on the exact edge and offset vectors; the region's barycentric
 // coordinates give the closest point, q - f(phi) = ap - phi1 ab - phi2 ac.
-template <bool GRAD>
-__device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, float qx, float qy,
-                                         float qz, const EvalArgs &A, float slogA, bool metric) {
+template <bool GRAD, class QT>
+__device__ __forceinline__ Term tri_term(float4 r0, float4 r1, float4 r2, QT qx, QT qy,
+                                         QT qz, const EvalArgs &A, float slogA, bool metric) {
     const float S = A.S, inv_alpha = A.inv_alpha;
     const double abx = (double)r1.x - (double)r0.x, aby = (double)r1.y - (double)r0.y,
                  abz = (double)r1.z - (double)r0.z;
@@ -818,47 +818,83 @@ __device__ __forceinline__ void traverse(const TreeView &T, const EvalArgs &A, f
 // a lower bound of the box distance that equals the point formula for a
 // point, and direction gap / |gap|.
 // ---------------------------------------------------------------------------
-struct V3 {
-    float x, y, z;
+// The closest-pair routines are written once for the scalar type R: the
+// query vertices travel in FP32 (V3), and the closest point g(lambda) is
+// formed in FP64 (V3D) from the exact FP64 vertices, so that it lies on g to
+// FP64 rounding and the term at it is exact to the FP64 arithmetic (an FP32
+// g(lambda) moves the distance by its rounding at first order where a vertex
+// or an edge of g is closest).  The degeneracy thresholds scale with R.
+template <class R>
+struct V3T {
+    R x, y, z;
 };
-__device__ __forceinline__ V3 v3m(float x, float y, float z) { return V3{x, y, z}; }
-__device__ __forceinline__ V3 vsub(V3 a, V3 b) { return v3m(a.x - b.x, a.y - b.y, a.z - b.z); }
-__device__ __forceinline__ V3 vaxpy(V3 a, float s, V3 e) {   // a + s e
-    return v3m(fmaf(s, e.x, a.x), fmaf(s, e.y, a.y), fmaf(s, e.z, a.z));
+using V3 = V3T<float>;
+using V3D = V3T<double>;
+template <class R> struct GeomTol;
+template <> struct GeomTol<float> {
+    static constexpr float tri = 1e-12f, par = 1e-6f, cross = 1e-12f;
+};
+template <> struct GeomTol<double> {
+    static constexpr double tri = 1e-20, par = 1e-14, cross = 1e-24;
+};
+__device__ __forceinline__ double dop(double a, double b, double c, double d) {
+    const double w = c * d;
+    return fma(a, b, -w) + fma(-c, d, w);
 }
-__device__ __forceinline__ float vdot(V3 a, V3 b) { return dot3(a.x, a.y, a.z, b.x, b.y, b.z); }
-__device__ __forceinline__ V3 vcross(V3 a, V3 b) {
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float rcpR(float x) { return frcp(x); }
+__device__ __forceinline__ double rcpR(double x) { return 1.0 / x; }
+__device__ __forceinline__ float med01(float x) { return __builtin_amdgcn_fmed3f(x, 0.f, 1.f); }
+__device__ __forceinline__ double med01(double x) { return fmin(fmax(x, 0.0), 1.0); }
+
+__device__ __forceinline__ V3 v3m(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3D v3m(double x, double y, double z) { return V3D{x, y, z}; }
+__device__ __forceinline__ V3D v3d(V3 a) { return V3D{(double)a.x, (double)a.y, (double)a.z}; }
+template <class R>
+__device__ __forceinline__ V3T<R> vsub(V3T<R> a, V3T<R> b) { return v3m(a.x - b.x, a.y - b.y, a.z - b.z); }
+template <class R>
+__device__ __forceinline__ V3T<R> vaxpy(V3T<R> a, R s, V3T<R> e) {   // a + s e
+    return v3m(fmaR(s, e.x, a.x), fmaR(s, e.y, a.y), fmaR(s, e.z, a.z));
+}
+template <class R>
+__device__ __forceinline__ R vdot(V3T<R> a, V3T<R> b) { return fmaR(a.x, b.x, fmaR(a.y, b.y, a.z * b.z)); }
+template <class R>
+__device__ __forceinline__ V3T<R> vcross(V3T<R> a, V3T<R> b) {
     return v3m(dop(a.y, b.z, a.z, b.y), dop(a.z, b.x, a.x, b.z), dop(a.x, b.y, a.y, b.x));
 }
-__device__ __forceinline__ float vdist2(V3 a, V3 b) {
-    V3 d = vsub(a, b);
+template <class R>
+__device__ __forceinline__ R vdist2(V3T<R> a, V3T<R> b) {
+    V3T<R> d = vsub(a, b);
     return vdot(d, d);
 }
 
 // closest point of segment a b to p
-__device__ __forceinline__ V3 seg_point(V3 p, V3 a, V3 b) {
-    V3 e = vsub(b, a);
-    float ee = vdot(e, e);
-    float t = ee > 0.f ? __builtin_amdgcn_fmed3f(fdiv(vdot(vsub(p, a), e), ee), 0.f, 1.f) : 0.f;
+template <class R>
+__device__ __forceinline__ V3T<R> seg_point(V3T<R> p, V3T<R> a, V3T<R> b) {
+    V3T<R> e = vsub(b, a);
+    R ee = vdot(e, e);
+    R t = ee > R(0) ? med01(vdot(vsub(p, a), e) * rcpR(ee)) : R(0);
     return vaxpy(a, t, e);
 }
 
 // closest point of triangle a b c to p: the plane projection when its
 // barycentrics are inside, else the closest of the three edges
-__device__ __forceinline__ V3 tri_point(V3 p, V3 a, V3 b, V3 c) {
-    V3 e1 = vsub(b, a), e2 = vsub(c, a), r = vsub(p, a);
-    float g11 = vdot(e1, e1), g12 = vdot(e1, e2), g22 = vdot(e2, e2);
-    float det = dop(g11, g22, g12, g12);
-    if (det > 1e-12f * g11 * g22) {
-        float r1 = vdot(e1, r), r2 = vdot(e2, r);
-        float inv = frcp(det);
-        float u = dop(g22, r1, g12, r2) * inv, v = dop(g11, r2, g12, r1) * inv;
-        if (u >= 0.f && v >= 0.f && u + v <= 1.f) return vaxpy(vaxpy(a, u, e1), v, e2);
+template <class R>
+__device__ __forceinline__ V3T<R> tri_point(V3T<R> p, V3T<R> a, V3T<R> b, V3T<R> c) {
+    V3T<R> e1 = vsub(b, a), e2 = vsub(c, a), r = vsub(p, a);
+    R g11 = vdot(e1, e1), g12 = vdot(e1, e2), g22 = vdot(e2, e2);
+    R det = dop(g11, g22, g12, g12);
+    if (det > GeomTol<R>::tri * g11 * g22) {
+        R r1 = vdot(e1, r), r2 = vdot(e2, r);
+        R inv = rcpR(det);
+        R u = dop(g22, r1, g12, r2) * inv, v = dop(g11, r2, g12, r1) * inv;
+        if (u >= R(0) && v >= R(0) && u + v <= R(1)) return vaxpy(vaxpy(a, u, e1), v, e2);
     }
-    V3 best = seg_point(p, a, b);
-    float bd = vdist2(p, best);
-    V3 y = seg_point(p, b, c);
-    float d = vdist2(p, y);
+    V3T<R> best = seg_point(p, a, b);
+    R bd = vdist2(p, best);
+    V3T<R> y = seg_point(p, b, c);
+    R d = vdist2(p, y);
     if (d < bd) { bd = d; best = y; }
     y = seg_point(p, c, a);
     d = vdist2(p, y);
@@ -869,16 +905,17 @@ __device__ __forceinline__ V3 tri_point(V3 p, V3 a, V3 b, V3 c) {
 // the interior stationary point of |x(s) - y(t)|^2 over the two segments, when
 // the segments are not (nearly) parallel and it lies inside both: squared
 // distance (else +inf), the point on q
-__device__ __forceinline__ float seg_seg_interior(V3 p0, V3 p1, V3 q0, V3 q1, V3 &on_q) {
-    V3 u = vsub(p1, p0), v = vsub(q1, q0), w = vsub(p0, q0);
-    float a = vdot(u, u), b = vdot(u, v), c = vdot(v, v), d = vdot(u, w), e = vdot(v, w);
-    float best = INFINITY;
-    float den = dop(a, c, b, b);
-    if (den > 1e-6f * a * c) {
-        float inv = frcp(den);
-        float s = dop(b, e, c, d) * inv, t = dop(a, e, b, d) * inv;
-        if (s >= 0.f && s <= 1.f && t >= 0.f && t <= 1.f) {
-            V3 x = vaxpy(p0, s, u), y = vaxpy(q0, t, v);
+template <class R>
+__device__ __forceinline__ R seg_seg_interior(V3T<R> p0, V3T<R> p1, V3T<R> q0, V3T<R> q1, V3T<R> &on_q) {
+    V3T<R> u = vsub(p1, p0), v = vsub(q1, q0), w = vsub(p0, q0);
+    R a = vdot(u, u), b = vdot(u, v), c = vdot(v, v), d = vdot(u, w), e = vdot(v, w);
+    R best = R(INFINITY);
+    R den = dop(a, c, b, b);
+    if (den > GeomTol<R>::par * a * c) {
+        R inv = rcpR(den);
+        R s = dop(b, e, c, d) * inv, t = dop(a, e, b, d) * inv;
+        if (s >= R(0) && s <= R(1) && t >= R(0) && t <= R(1)) {
+            V3T<R> x = vaxpy(p0, s, u), y = vaxpy(q0, t, v);
             best = vdist2(x, y);
             on_q = y;
         }
@@ -888,10 +925,11 @@ __device__ __forceinline__ float seg_seg_interior(V3 p0, V3 p1, V3 q0, V3 q1, V3
 
 // closest points of segments p0 p1 and q0 q1: the interior stationary point or
 // an endpoint of one against the other; squared distance, point on q
-__device__ __forceinline__ float seg_seg(V3 p0, V3 p1, V3 q0, V3 q1, V3 &on_q) {
-    float best = seg_seg_interior(p0, p1, q0, q1, on_q);
-    V3 y = seg_point(p0, q0, q1);
-    float dd = vdist2(p0, y);
+template <class R>
+__device__ __forceinline__ R seg_seg(V3T<R> p0, V3T<R> p1, V3T<R> q0, V3T<R> q1, V3T<R> &on_q) {
+    R best = seg_seg_interior(p0, p1, q0, q1, on_q);
+    V3T<R> y = seg_point(p0, q0, q1);
+    R dd = vdist2(p0, y);
     if (dd < best) { best = dd; on_q = y; }
     y = seg_point(p1, q0, q1);
     dd = vdist2(p1, y);
@@ -906,13 +944,15 @@ __device__ __forceinline__ float seg_seg(V3 p0, V3 p1, V3 q0, V3 q1, V3 &on_q) {
 // Quantities of a triangle a b c shared by every test against it: edge
 // vectors e1 = b - a, e2 = c - a, their Gram entries, the reciprocal of the
 // Gram determinant (0 for a degenerate triangle) and the normal e1 x e2.
+template <class R>
 struct TriFrame {
-    V3 a, e1, e2, n;
-    float g11, g12, g22, inv;
+    V3T<R> a, e1, e2, n;
+    R g11, g12, g22, inv;
     bool ok;
 };
-__device__ __forceinline__ TriFrame tri_frame(V3 a, V3 b, V3 c) {
-    TriFrame f;
+template <class R>
+__device__ __forceinline__ TriFrame<R> tri_frame(V3T<R> a, V3T<R> b, V3T<R> c) {
+    TriFrame<R> f;
     f.a = a;
     f.e1 = vsub(b, a);
     f.e2 = vsub(c, a);
@@ -920,30 +960,33 @@ __device__ __forceinline__ TriFrame tri_frame(V3 a, V3 b, V3 c) {
     f.g11 = vdot(f.e1, f.e1);
     f.g12 = vdot(f.e1, f.e2);
     f.g22 = vdot(f.e2, f.e2);
-    float det = dop(f.g11, f.g22, f.g12, f.g12);
-    f.ok = det > 1e-12f * f.g11 * f.g22;
-    f.inv = f.ok ? frcp(det) : 0.f;
+    R det = dop(f.g11, f.g22, f.g12, f.g12);
+    f.ok = det > GeomTol<R>::tri * f.g11 * f.g22;
+    f.inv = f.ok ? rcpR(det) : R(0);
     return f;
 }
 
 // Projection y of p onto the plane of the triangle; true when it falls inside
 // the triangle (the face region; tri_point's inside test)
-__device__ __forceinline__ bool face_proj(const TriFrame &f, V3 p, V3 &y) {
-    V3 r = vsub(p, f.a);
-    float r1 = vdot(f.e1, r), r2 = vdot(f.e2, r);
-    float u = dop(f.g22, r1, f.g12, r2) * f.inv, v = dop(f.g11, r2, f.g12, r1) * f.inv;
+template <class R>
+__device__ __forceinline__ bool face_proj(const TriFrame<R> &f, V3T<R> p, V3T<R> &y) {
+    V3T<R> r = vsub(p, f.a);
+    R r1 = vdot(f.e1, r), r2 = vdot(f.e2, r);
+    R u = dop(f.g22, r1, f.g12, r2) * f.inv, v = dop(f.g11, r2, f.g12, r1) * f.inv;
     y = vaxpy(vaxpy(f.a, u, f.e1), v, f.e2);
-    return f.ok && u >= 0.f && v >= 0.f && u + v <= 1.f;
+    return f.ok && u >= R(0) && v >= R(0) && u + v <= R(1);
 }
 
 // Segment p0 p1 crossing the triangle t0 t1 t2 (frame f): the crossing point,
 // accepted when it lies on the triangle up to rounding
-__device__ __forceinline__ bool seg_crosses(V3 p0, V3 p1, const TriFrame &f, V3 t0, V3 t1, V3 t2, V3 &y) {
-    float s0 = vdot(f.n, vsub(p0, f.a)), s1 = vdot(f.n, vsub(p1, f.a));
-    if (!((s0 <= 0.f && s1 >= 0.f) || (s0 >= 0.f && s1 <= 0.f)) || s0 == s1) return false;
+template <class R>
+__device__ __forceinline__ bool seg_crosses(V3T<R> p0, V3T<R> p1, const TriFrame<R> &f, V3T<R> t0, V3T<R> t1,
+                                            V3T<R> t2, V3T<R> &y) {
+    R s0 = vdot(f.n, vsub(p0, f.a)), s1 = vdot(f.n, vsub(p1, f.a));
+    if (!((s0 <= R(0) && s1 >= R(0)) || (s0 >= R(0) && s1 <= R(0))) || s0 == s1) return false;
     y = vaxpy(p0, s0 / (s0 - s1), vsub(p1, p0));
-    V3 z = tri_point(y, t0, t1, t2);
-    return vdist2(y, z) <= 1e-12f * (1.f + vdot(y, y));
+    V3T<R> z = tri_point(y, t0, t1, t2);
+    return vdist2(y, z) <= GeomTol<R>::cross * (R(1) + vdot(y, y));
 }
 
 // Segment p0 p1 against triangle t0 t1 t2: squared distance, the closest point
@@ -951,26 +994,28 @@ __device__ __forceinline__ bool seg_crosses(V3 p0, V3 p1, const TriFrame &f, V3 
 // from a crossing, the closest pair is an endpoint against the face interior
 // or the segment against one of the triangle's edges (App. B's QP optimum lies
 // on those boundary faces).
-__device__ __forceinline__ float seg_tri(V3 p0, V3 p1, V3 t0, V3 t1, V3 t2, V3 &xs, V3 &xt) {
-    const TriFrame f = tri_frame(t0, t1, t2);
-    V3 y;
+template <class R>
+__device__ __forceinline__ R seg_tri(V3T<R> p0, V3T<R> p1, V3T<R> t0, V3T<R> t1, V3T<R> t2, V3T<R> &xs,
+                                     V3T<R> &xt) {
+    const TriFrame<R> f = tri_frame(t0, t1, t2);
+    V3T<R> y;
     if (seg_crosses(p0, p1, f, t0, t1, t2, y)) {
         xs = y;
         xt = y;
-        return 0.f;
+        return R(0);
     }
-    float best = INFINITY;
+    R best = R(INFINITY);
     xs = p0;
     xt = t0;
     if (face_proj(f, p0, y)) { best = vdist2(p0, y); xt = y; }
     if (face_proj(f, p1, y)) {
-        float d = vdist2(p1, y);
+        R d = vdist2(p1, y);
         if (d < best) { best = d; xs = p1; xt = y; }
     }
-    V3 T3[3] = {t0, t1, t2};
+    V3T<R> T3[3] = {t0, t1, t2};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        float d = seg_seg(T3[k], T3[(k + 1) % 3], p0, p1, y);   // y on p0 p1
+        R d = seg_seg(T3[k], T3[(k + 1) % 3], p0, p1, y);   // y on p0 p1
         if (d < best) {
             best = d;
             xs = y;
@@ -983,27 +1028,28 @@ __device__ __forceinline__ float seg_tri(V3 p0, V3 p1, V3 t0, V3 t1, V3 t2, V3 &
 // Triangle g against triangle t: the point of g closest to t.  The triangles
 // meet when an edge of one crosses the other; otherwise the closest pair is a
 // vertex of one against the other's face interior, or a pair of edges.
-__device__ __forceinline__ V3 tri_tri_on_g(const V3 (&t)[3], const V3 (&g)[3]) {
-    const TriFrame ft = tri_frame(t[0], t[1], t[2]), fg = tri_frame(g[0], g[1], g[2]);
-    V3 y;
+template <class R>
+__device__ __forceinline__ V3T<R> tri_tri_on_g(const V3T<R> (&t)[3], const V3T<R> (&g)[3]) {
+    const TriFrame<R> ft = tri_frame(t[0], t[1], t[2]), fg = tri_frame(g[0], g[1], g[2]);
+    V3T<R> y;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         if (seg_crosses(g[k], g[(k + 1) % 3], ft, t[0], t[1], t[2], y)) return y;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         if (seg_crosses(t[k], t[(k + 1) % 3], fg, g[0], g[1], g[2], y)) return y;
-    float best = INFINITY;
-    V3 out = g[0];
+    R best = R(INFINITY);
+    V3T<R> out = g[0];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         if (face_proj(ft, g[k], y)) {
-            float d = vdist2(g[k], y);
+            R d = vdist2(g[k], y);
             if (d < best) { best = d; out = g[k]; }
         }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         if (face_proj(fg, t[k], y)) {
-            float d = vdist2(t[k], y);
+            R d = vdist2(t[k], y);
             if (d < best) { best = d; out = y; }
         }
     // edge pairs: the interior stationary points, then each vertex of one
@@ -1013,7 +1059,7 @@ __device__ __forceinline__ V3 tri_tri_on_g(const V3 (&t)[3], const V3 (&g)[3]) {
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            float d = seg_seg_interior(t[i], t[(i + 1) % 3], g[j], g[(j + 1) % 3], y);   // y on g's edge
+            R d = seg_seg_interior(t[i], t[(i + 1) % 3], g[j], g[(j + 1) % 3], y);   // y on g's edge
             if (d < best) { best = d; out = y; }
         }
 #pragma unroll
@@ -1021,7 +1067,7 @@ __device__ __forceinline__ V3 tri_tri_on_g(const V3 (&t)[3], const V3 (&g)[3]) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             y = seg_point(t[i], g[j], g[(j + 1) % 3]);
-            float d = vdist2(t[i], y);
+            R d = vdist2(t[i], y);
             if (d < best) { best = d; out = y; }
             d = vdist2(g[j], seg_point(g[j], t[i], t[(i + 1) % 3]));
             if (d < best) { best = d; out = g[j]; }
@@ -1036,10 +1082,10 @@ struct QPrim {
 };
 
 // The point of the query primitive (vertices gv) closest to the data primitive
-// (vertices dv: 1 point, 2 edge, 3 triangle), all in one frame.
+// (vertices dv: 1 point, 2 edge, 3 triangle), all in one frame, in FP64.
 template <int CLS, int NV>
-__device__ __forceinline__ V3 closest_on_query(const V3 (&dv)[3], const V3 (&gv)[NV]) {
-    V3 y, xs, xt;
+__device__ __forceinline__ V3D closest_on_query(const V3D (&dv)[3], const V3D (&gv)[NV]) {
+    V3D y, xs, xt;
     if (CLS == 0) return NV == 2 ? seg_point(dv[0], gv[0], gv[1]) : tri_point(dv[0], gv[0], gv[1], gv[NV - 1]);
     if (CLS == 1) {
         if (NV == 2) {
@@ -1053,16 +1099,17 @@ __device__ __forceinline__ V3 closest_on_query(const V3 (&dv)[3], const V3 (&gv)
         seg_tri(gv[0], gv[1], dv[0], dv[1], dv[2], xs, xt);
         return xs;
     }
-    const V3 g3[3] = {gv[0], gv[1], gv[NV - 1]};
+    const V3D g3[3] = {gv[0], gv[1], gv[NV - 1]};
     return tri_tri_on_g(dv, g3);
 }
 
-// Leaf term for a query primitive: the point-query term at g(lambda).  Both
-// primitives are moved into the frame of the data primitive's first vertex
-// before anything is formed, so that g(lambda) carries rounding of the size
-// of the local offsets rather than of the absolute coordinates (the terms are
-// translation invariant; the weight data in .w is kept); the rounding of
-// g(lambda) lowers the distance bound by 2^-20 |g(lambda)|_1.
+// Leaf term for a query primitive: the point-query term at g(lambda), the
+// point of g closest to the data primitive.  The closest pair is solved in
+// FP64 in the frame of the data primitive's first vertex o (the vertex
+// differences are exact in FP64), and the term is formed from the data
+// primitive's own records and o + g(lambda); a rounding of g(lambda) of
+// 2^-50 of the local offsets, and the skipped interior stationary points of
+// nearly parallel edges, lower the distance bound by 2^-24 |g(lambda) - o|_1.
 template <int CLS, bool GRAD, int NV>
 __device__ __forceinline__ Term leaf_term_q(const TreeView &T, const EvalArgs &A, int slot, float4 leaf_lo,
                                             const QPrim<NV> &g, bool metric) {
@@ -1078,25 +1125,25 @@ __device__ __forceinline__ Term leaf_term_q(const TreeView &T, const EvalArgs &A
         r[2] = T.leaf[3 * slot + 2];
     }
     constexpr int ND = CLS + 1;
-    const V3 o = v3m(r[0].x, r[0].y, r[0].z);
-    V3 dv[3], gv[NV];
-    dv[0] = v3m(0.f, 0.f, 0.f);
+    const V3D o = v3m((double)r[0].x, (double)r[0].y, (double)r[0].z);
+    V3D dv[3], gv[NV];
+    dv[0] = v3m(0.0, 0.0, 0.0);
 #pragma unroll
-    for (int k = 1; k < 3; ++k) dv[k] = k < ND ? vsub(v3m(r[k].x, r[k].y, r[k].z), o) : dv[0];
+    for (int k = 1; k < 3; ++k)
+        dv[k] = k < ND ? vsub(v3m((double)r[k].x, (double)r[k].y, (double)r[k].z), o) : dv[0];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) gv[k] = vsub(g.v[k], o);
-    V3 q = closest_on_query<CLS, NV>(dv, gv);
+    for (int k = 0; k < NV; ++k) gv[k] = vsub(v3d(g.v[k]), o);
+    const V3D ql = closest_on_query<CLS, NV>(dv, gv);
+    const double qx = o.x + ql.x, qy = o.y + ql.y, qz = o.z + ql.z;
     Term t;
     if (CLS == 0) {
-        t = point_term<GRAD>(make_float4(0.f, 0.f, 0.f, r[0].w), q.x, q.y, q.z);
+        t = point_term<GRAD>(r[0], qx, qy, qz);
     } else if (CLS == 1) {
-        t = edge_term<GRAD>(make_float4(0.f, 0.f, 0.f, r[0].w), make_float4(dv[1].x, dv[1].y, dv[1].z, r[1].w),
-                            q.x, q.y, q.z, A.S, (float)T.slogA, A.inv_alpha, metric);
+        t = edge_term<GRAD>(r[0], r[1], qx, qy, qz, A.S, (float)T.slogA, A.inv_alpha, metric);
     } else {
-        t = tri_term<GRAD>(make_float4(0.f, 0.f, 0.f, r[0].w), make_float4(dv[1].x, dv[1].y, dv[1].z, r[1].w),
-                           make_float4(dv[2].x, dv[2].y, dv[2].z, r[2].w), q.x, q.y, q.z, A, (float)T.slogA, metric);
+        t = tri_term<GRAD>(r[0], r[1], r[2], qx, qy, qz, A, (float)T.slogA, metric);
     }
-    t.dlo = fmaf(-0x1p-20f, fabsf(q.x) + fabsf(q.y) + fabsf(q.z), t.dlo);
+    t.dlo = fmaf(-0x1p-24f, (float)(fabs(ql.x) + fabs(ql.y) + fabs(ql.z)), t.dlo);
     return t;
 }
 
@@ -1412,12 +1459,12 @@ k_query_keys(const float *__restrict__ Q, const uint32_t *__restrict__ idx, int6
 // inside this kernel; a lane whose ray has ended leaves the loop, and the
 // traversal's wave-cooperative leaf stage works with the lanes still present.
 // value + gradient for query primitives with NV vertices (G: n x NV x 3)
-// Compiled for four waves per SIMD (at most 128 registers): the default
-// allocation takes 132-156 registers for edge and triangle data, three waves,
-// and the fourth wave's latency hiding is worth about 10 % (the few spills of
-// the triangle-on-triangle variants included).
+// Compiled for three waves per SIMD (at most 168 registers): the FP64
+// closest-pair geometry spills heavily within 128 registers (up to 290 for
+// triangles on triangles), and the third wave's budget is about 10 % faster
+// for edges and triangles as queries than the fourth wave's.
 template <int NV, int MASK>
-__global__ void __launch_bounds__(kEB) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(kEB) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_evalq(EvalArgs A, const float *__restrict__ G) {
     int i = xcd_block(blockIdx.x, gridDim.x) * kEB + threadIdx.x;
     if (i >= A.nthr) return;
