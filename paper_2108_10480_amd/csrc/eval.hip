@@ -844,7 +844,16 @@ __device__ __forceinline__ double dop(double a, double b, double c, double d) {
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float rcpR(float x) { return frcp(x); }
-__device__ __forceinline__ double rcpR(double x) { return 1.0 / x; }
+// FP64 reciprocal: the hardware estimate and two Newton steps (each squares
+// the relative error), instead of the correctly rounded division sequence;
+// the closest-pair parameters need no correct rounding.
+__device__ __forceinline__ double rcpR(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 __device__ __forceinline__ float med01(float x) { return __builtin_amdgcn_fmed3f(x, 0.f, 1.f); }
 __device__ __forceinline__ double med01(double x) { return fmin(fmax(x, 0.0), 1.0); }
 
@@ -984,7 +993,7 @@ __device__ __forceinline__ bool seg_crosses(V3T<R> p0, V3T<R> p1, const TriFrame
                                             V3T<R> t2, V3T<R> &y) {
     R s0 = vdot(f.n, vsub(p0, f.a)), s1 = vdot(f.n, vsub(p1, f.a));
     if (!((s0 <= R(0) && s1 >= R(0)) || (s0 >= R(0) && s1 <= R(0))) || s0 == s1) return false;
-    y = vaxpy(p0, s0 / (s0 - s1), vsub(p1, p0));
+    y = vaxpy(p0, s0 * rcpR(s0 - s1), vsub(p1, p0));
     V3T<R> z = tri_point(y, t0, t1, t2);
     return vdist2(y, z) <= GeomTol<R>::cross * (R(1) + vdot(y, y));
 }
