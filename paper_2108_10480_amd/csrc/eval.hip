@@ -837,10 +837,9 @@ template <> struct GeomTol<float> {
 template <> struct GeomTol<double> {
     static constexpr double tri = 1e-20, par = 1e-14, cross = 1e-24;
 };
-__device__ __forceinline__ double dop(double a, double b, double c, double d) {
-    const double w = c * d;
-    return fma(a, b, -w) + fma(-c, d, w);
-}
+// a b - c d in FP64: one rounded product and one FMA (the FP32 form above
+// keeps the product's rounding error; FP64 has the margin without it)
+__device__ __forceinline__ double dop(double a, double b, double c, double d) { return fma(a, b, -(c * d)); }
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float rcpR(float x) { return frcp(x); }
