@@ -73,10 +73,10 @@ def test_triangle_query_mesh_end_to_end(beta):
     and gradients of its triangles from the query-primitive traversal
     (Sec. 3.4), combined by Eq. 6-8, against the oracle's query-primitive
     Barnes-Hut (FP32 opening decisions) combined by the oracle's Eq. 6-8.
-    Tolerances follow from the per-primitive ones (value 2e-5, gradient 1e-3
-    for triangles on triangles): D is a log-sum-exp of the d_j, so its
-    relative error is at most theirs; w_j = softmin weights move by about
-    alpha_q |delta d_j|; the vertex gradients mix the gradient errors."""
+    Tolerances follow from the per-primitive ones (the 1e-5 gate for value
+    and gradient): D is a log-sum-exp of the d_j, so its relative error is at
+    most theirs; w_j = softmin weights move by about alpha_q |delta d_j|; the
+    vertex gradients mix the gradient errors (relative to the largest)."""
     require_gpu()
     from tests.gpu_common import oracle_trees
     data = scenes.bumpy_icosphere(level=3, seed=5)
@@ -95,10 +95,12 @@ def test_triangle_query_mesh_end_to_end(beta):
     assert dm.min() > 0.1
     Dr, wr, vr = QM.query_mesh_lse(dr[None], gr[None], alpha_q, tf.astype(np.int64), len(tv))
     D, w, vg = D.cpu().numpy().astype(np.float64), w.cpu().numpy(), vg.cpu().numpy()
-    assert abs(D[0] - Dr[0]) <= 2e-5 * abs(Dr[0])
+    ev, eg = abs(D[0] - Dr[0]) / abs(Dr[0]), np.abs(vg[0] - vr[0]).max() / np.abs(vr).max()
+    print(f"query mesh beta={beta}: D relative error {ev:.2e}, vertex gradient error {eg:.2e} of the largest")
+    assert ev <= 1e-5
     dd = np.abs(d.cpu().numpy() - dr).max()
     np.testing.assert_allclose(w[0], wr[0], rtol=0, atol=3 * alpha_q * dd * wr.max() + 1e-7)
-    np.testing.assert_allclose(vg[0], vr[0], rtol=0, atol=1e-3 * np.abs(vr).max())
+    assert eg <= 1e-5
 
 
 def test_edge_cases():
